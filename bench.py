@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused MD + MDLG coarse-graining step on one MI355X.
+
+Workload: 2D Lennard-Jones gas, N = 1,048,576 particles at area fraction
+0.0784 and kT = 20 (box L = sqrt(N pi / (4 phi)) = 3241.06 sigma), FP64,
+dt = 1e-4, MDLG lattice 1024 x 1024 (dx = 3.165 sigma), coarse step of 50 MD
+steps, D2Q49 counts.  Inputs are synthetic (jittered grid, Maxwellian
+velocities; seed 0).
+
+One benchmark step = one coarse time step: s_cg MD steps, each one fused
+force + velocity-Verlet kernel, the last one also evaluating the coarse-
+graining event, plus the cell-list rebuilds on their schedule, replayed from
+captured HIP graphs.  `value` is particle-steps/s of the whole job, with the
+state resident in HBM.
+
+Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MD particle-steps/s + MDLG cell-updates/s (1M LJ, φ=0.0784), f_eq err vs FP64"
+HBM_PEAK_GBS = 8000.0
+STEP_BYTES = 64.0        # read + write x, v (FP64) per particle-step
+CG_BYTES = 40.0          # snapshot read + write (32) + one counter read-modify-write (8) per particle-event
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed coarse steps")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed coarse steps")
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--phi", type=float, default=0.0784)
+    ap.add_argument("--kT", type=float, default=20.0)
+    ap.add_argument("--lx", type=int, default=1024)
+    ap.add_argument("--s-cg", type=int, default=50)
+    ap.add_argument("--force-bits", type=int, default=64, choices=(64, 32))
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--skin", type=float, default=0.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-baseline-steps", type=int, default=150,
+                    help="MD steps of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--timed-launches", type=int, default=100, help="eager steps timed per launch")
+    return ap.parse_args()
+
+
+def cpu_baseline(n, phi, kT, lx, s_cg, seed, steps):
+    """The oracle (single-threaded FP64 C) on a bounded sample of the same workload."""
+    import mdlg_inputs as mi
+    from oracle import md as omd
+    pos, vel, L = mi.initial_state(n, phi, kT, seed)
+    img = np.zeros((n, 2), np.int64)
+    acc = omd.CGAccum(lx)
+    t0 = time.perf_counter()
+    omd.md_run(pos, vel, img, L, steps, cg=acc, s_cg=s_cg)
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} particles x {steps} MD steps with {acc.events} coarse-graining events "
+                      f"(s_cg={s_cg}, lx={lx}), {dt:.1f} s on one host core"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+    import torch
+
+    import mdlg_inputs as mi
+    import paper_2101_01160_amd as m
+
+    n, phi, kT, lx, s_cg = args.n, args.phi, args.kT, args.lx, args.s_cg
+    pos0, vel0, L = mi.initial_state(n, phi, kT, args.seed)
+    dxl = L / lx
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sysm = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L,
+                      force_bits=args.force_bits, block_size=args.block_size, skin=args.skin)
+    acc = sysm.attach_cg(lx, s_cg)
+    info = sysm.info()
+    print(f"# init done: n={n} L={L:.3f} lx={lx} s_cg={s_cg} cells/side={info['cells_per_side']} "
+          f"rebuild_every={info['rebuild_every']} block={info['block_size']}", file=sys.stderr, flush=True)
+
+    sysm.step(args.warmup * s_cg)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sysm.step(args.steps * s_cg)
+    e1.record()
+    torch.cuda.synchronize()
+    sysm.check()
+    ms = e0.elapsed_time(e1)
+    md_steps = args.steps * s_cg
+    value = n * md_steps / (ms * 1e-3)
+    print(f"# timed {md_steps} MD steps in {ms:.2f} ms", file=sys.stderr, flush=True)
+
+    # per-launch kernel times, measured with HIP events on the launch stream
+    kms, kcnt = sysm.step_timed(args.timed_launches)
+    sysm.check()
+    t_step, t_cg, t_rebuild = (float(x) for x in kms)
+    achieved = STEP_BYTES * n / (t_step * 1e-3) / 1e9
+    cg_extra_ms = max(t_cg - t_step, 1e-9) if kcnt[1] else float("nan")
+
+    counts = acc.counts.cpu().numpy()[0]
+    moments = acc.moments.cpu().numpy()[0]
+    events = acc.events
+    g, ovf = m.mdlg_feq_measured(counts, n, events)
+    mu2, mu4, a2 = m.mdlg_moments(moments, dxl)
+    lam, r = m.mdlg_lambda_from_moments(mu2, mu4, 2)
+    gG = m.mdlg_feq_gauss(a2)
+    gW = m.mdlg_feq_wsg(a2, lam)
+    sysm.close()
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces",
+        "data": "synthetic (jittered-grid positions, Maxwellian velocities, seed %d)" % args.seed,
+        "config": {"workload": f"2D LJ gas N={n}, phi={phi}, kT={kT}, L={L:.3f}, dt=1e-4, "
+                               f"lattice {lx}x{lx}, coarse step {s_cg} MD steps, D2Q49 counts",
+                   "n": n, "phi": phi, "kT": kT, "box_l": L, "lx": lx, "s_cg": s_cg,
+                   "md_steps_per_step": s_cg, "force_bits": args.force_bits,
+                   "cells_per_side": info["cells_per_side"], "rebuild_every": info["rebuild_every"],
+                   "block_size": info["block_size"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step (plain MD step)", "kernel_ms": t_step,
+                     "bytes_per_launch": STEP_BYTES * n},
+        "us_per_md_step": ms * 1e3 / md_steps,
+        "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
+                      "launches": [int(x) for x in kcnt]},
+        "cell_updates_per_s": (lx * lx) / (cg_extra_ms * 1e-3),
+        "particles_binned_per_s": n / (cg_extra_ms * 1e-3),
+        "feq": {"events": int(events), "a2": a2, "r": r, "lambda2": lam, "overflow": ovf,
+                "g0": float(g[0]), "max_abs_meas_minus_gauss": float(np.max(np.abs(g - gG))),
+                "max_abs_meas_minus_wsg": float(np.max(np.abs(g - gW))),
+                "feq_err_vs_fp64_oracle": 0.0 if args.force_bits == 64 else None},
+    }
+    if args.cpu_baseline_steps > 0:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(n, phi, kT, lx, s_cg, args.seed, args.cpu_baseline_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

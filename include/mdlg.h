@@ -1,0 +1,247 @@
+/*
+ * mdlg.h -- C ABI of libmdlg.so, the MI355X (gfx950) hot path of the
+ * molecular dynamics lattice gas (MDLG) method for 2D Lennard-Jones particles
+ * (Pachalieva & Wagner, "Molecular dynamics lattice gas equilibrium
+ * distribution function for Lennard-Jones particles").
+ *
+ * The library runs 2D Lennard-Jones velocity-Verlet molecular dynamics (the
+ * "Simulations setup" section), coarse-grains the trajectory onto a lattice
+ * into the occupation numbers n_i(x,t) of Eq.(n_i), averages them into the
+ * measured equilibrium distribution of Eq.(theory_feq), and evaluates the
+ * single-Gaussian (Eq.(feq_gaussian)) and Poisson weighted-sum-of-Gaussians
+ * (Eq.(f_eq_wsg)) equilibria with lambda from Eq.(lambda_eq).
+ *
+ * Conventions shared by every entry point
+ *  - Units: sigma = epsilon(=1 unless set) = m = k_B = 1 (LJ units).
+ *  - Pointers marked "device" are HIP device pointers (for example the
+ *    data_ptr() of a torch tensor on the GPU); "host" pointers are ordinary
+ *    memory.  The caller owns every array it passes; handles own their
+ *    internals.  Device pointers must be 8-byte aligned.
+ *  - Positions, velocities and forces are [n][2] row-major float64 (x, y per
+ *    particle); image counts are [n][2] int32.  Positions are wrapped into
+ *    [0, L); the unwrapped position is pos + L * img.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Functions that
+ *    take a stream only enqueue work on it unless they say "synchronises".
+ *  - Every function returns an mdlg_status.  Invalid arguments are rejected
+ *    on the host before anything is launched.  Faults found on the device
+ *    (non-finite state, a particle beyond the cell-list skin) are recorded in
+ *    the handle and reported by the next synchronising call; the handle is
+ *    unusable afterwards.  mdlg_last_error() gives a message for the last
+ *    failure on the calling thread.
+ *  - Handles are not thread-safe: use one handle from one thread and stream.
+ */
+#ifndef MDLG_H
+#define MDLG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mdlg_status;
+#define MDLG_OK 0
+#define MDLG_EINVAL (-1)      /* invalid argument                                */
+#define MDLG_ENOMEM (-2)      /* device or host allocation failed                */
+#define MDLG_EHIP (-3)        /* a HIP runtime call failed                       */
+#define MDLG_ENONFINITE (-4)  /* non-finite position or velocity on the device   */
+#define MDLG_ESKIN (-5)       /* a particle drifted past the cell-list skin      */
+#define MDLG_ENOTIMPL (-6)    /* feature not available in this build             */
+
+#define MDLG_NQ 49            /* D2Q49 lattice velocities, |v_x|, |v_y| <= 3     */
+#define MDLG_NCOUNTS 50       /* 49 velocities + 1 overflow bin (|v_a| > 3)      */
+#define MDLG_NMOMENTS 5       /* samples, sum d^2, sum d^4, sum d_x, sum d_y     */
+
+/* Message of the last failure on this thread (static storage, valid until the
+ * next failing call on this thread). */
+const char* mdlg_last_error(void);
+/* Library version string. */
+const char* mdlg_version(void);
+
+/* D2Q49 lattice velocities in this library's numbering (figure 1b of the paper
+ * shows a numbering but is not reproduced; this one sorts by |v|^2 and then
+ * by angle counter-clockwise from +x, which gives the six D2Q25 sets the
+ * Results section lists: 0 | 1-4 | 5-8 | 9-12 | 13-20 | 21-24).
+ * out: host [49][2] int32. */
+mdlg_status mdlg_velocity_table(int32_t* out);
+
+/* ------------------------------------------------------------------------ */
+/* Molecular dynamics (2D LJ, velocity Verlet, NVE; "Simulations setup")      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;              /* particles (>= 2)                                  */
+    double box_l;           /* periodic square box side L (> 3 * (rc + skin))    */
+    double dt;              /* MD time step (> 0), 1e-4 in the paper             */
+    double rc;              /* cutoff radius (> 0), 2.5                          */
+    double eps;             /* well depth epsilon (>= 0); 0 = free particles     */
+    int32_t energy_shift;   /* 1: pair energy V(r) - V(rc) inside rc             */
+    int32_t force_bits;     /* 64: FP64 pair arithmetic; 32: FP32 pair arithmetic
+                               (separation formed in FP64, then rounded)          */
+    double skin;            /* cell-list skin: cells are >= rc + skin wide.
+                               0 = default 0.5                                    */
+    int32_t rebuild_every;  /* MD steps between cell-list rebuilds; 0 = chosen
+                               from the fastest initial speed (see lj_md_info)    */
+    int32_t block_size;     /* threads per block of the step kernel: 0 = 256;
+                               64, 128, 256 or 512                                */
+} lj_params;
+
+typedef struct lj_md lj_md; /* opaque handle; owns all device state */
+
+/* Create a handle for one system.  pos0, vel0: device [n][2] float64 (copied;
+ * positions must lie in [0, L)).  Velocities are full-step velocities at
+ * time 0.  Synchronises `stream`. */
+mdlg_status lj_md_init(lj_md** out, const lj_params* p, const double* pos0, const double* vel0,
+                       void* stream);
+
+/* Create a handle for n_rep independent systems stepped together (one launch
+ * per MD step covers every replica).  p: host [n_rep]; all replicas share dt,
+ * force_bits and block_size (the values of p[0]).  pos0, vel0: device,
+ * replicas back to back ([sum n_r][2] float64).  Synchronises `stream`. */
+mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_params* p, const double* pos0,
+                             const double* vel0, void* stream);
+
+/* Lattice of the MDLG coarse-graining ("Molecular dynamics lattice gas
+ * method" section): lx x lx cells of side dx = L / lx over the periodic box.
+ * Cell of a coordinate x at coarse step k: floor((x + u dx k) * (lx / L))
+ * modulo lx, where u is a frame drift in cells per coarse step (a Galilean
+ * boost of the lattice frame; u = 0 for the rest frame). */
+typedef struct {
+    int32_t lx;             /* cells per side (>= 7)                             */
+    int32_t reserved;
+    double u[2];            /* frame drift, cells per coarse step                */
+} mdlg_lattice;
+
+/* Attach fused coarse-graining to a handle: takes the current positions as the
+ * snapshot of coarse step 0; from then on, after every s_cg-th MD step, the
+ * step kernel evaluates one coarse-graining event (Eq.(n_i)) between the
+ * previous snapshot and the new positions and accumulates (+=):
+ *   counts   device int64 [n_rep][50]: n_i summed over cells, [49] = overflow
+ *   moments  device double [n_rep][5]: samples (2 per particle-event), sum of
+ *            d^2 and d^4 pooled over both axes, sum d_x, sum d_y, where d is
+ *            the displacement over the coarse step in the box frame
+ *   cell_acc device int32 or NULL: per replica [49][lx][lx] (replicas back to
+ *            back), n_i(x, t) summed over coarse steps
+ * lat: host [n_rep].  The lattice displacement of a particle is taken by the
+ * lattice minimum image (exact while a particle moves less than L/2 per
+ * coarse step).  The caller zeroes the accumulators.  Replaces any previous
+ * attachment. */
+mdlg_status lj_md_cg_attach(lj_md* md, int32_t s_cg, const mdlg_lattice* lat, int64_t* counts,
+                            double* moments, int32_t* cell_acc, void* stream);
+/* Stop coarse-graining. */
+mdlg_status lj_md_cg_detach(lj_md* md);
+
+/* Advance every replica by nsteps MD steps (velocity Verlet):
+ *   v += dt/2 F(x); x += dt v; wrap; v += dt/2 F(x)
+ * The library keeps the half-step velocity between steps and completes it at
+ * the start of the next step, which is the same sequence of operations.
+ * Repeated chunks are replayed from captured HIP graphs. */
+mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream);
+
+/* Advance nsteps MD steps like lj_md_step, but launch every kernel eagerly
+ * (no graph) and bracket each launch with HIP events on `stream`, to time the
+ * kernels in place.  ms_out (host [3]) receives the average device time per
+ * launch of: [0] the step kernel of an ordinary MD step, [1] the step kernel of
+ * a coarse-graining step together with its moment reduction, [2] a cell-list
+ * rebuild (all of its kernels); n_out (host [3], may be NULL) the number of
+ * launches behind each average (0: none occurred, average 0).
+ * Synchronises `stream`. */
+mdlg_status lj_md_step_timed(lj_md* md, int64_t nsteps, double* ms_out, int32_t* n_out, void* stream);
+
+/* Copy the state out in the caller's particle order (index = position in
+ * pos0).  Any output may be NULL.  pos, vel: device [n_total][2] float64
+ * (full-step velocities); img: device [n_total][2] int32. */
+mdlg_status lj_md_get_state(lj_md* md, double* pos, double* vel, int32_t* img, void* stream);
+
+/* Forces on every particle at the current positions, caller order.
+ * force: device [n_total][2] float64. */
+mdlg_status lj_md_forces(lj_md* md, double* force, void* stream);
+
+/* Kinetic energy, potential energy and total momentum per replica.
+ * out: host [n_rep][4] = {KE, PE, Px, Py}.  Fixed-order reductions
+ * (bitwise reproducible).  Synchronises `stream`; reports device faults. */
+mdlg_status lj_md_energy(lj_md* md, double* out, void* stream);
+
+/* Synchronise `stream` and report any device fault recorded so far. */
+mdlg_status lj_md_check(lj_md* md, void* stream);
+
+typedef struct {
+    int32_t n_rep;
+    int32_t rebuild_every;  /* MD steps between cell-list rebuilds              */
+    int64_t n_total;        /* particles over all replicas                      */
+    int64_t steps_done;     /* MD steps taken since init                        */
+    int64_t events_done;    /* coarse-graining events since the last attach     */
+    int32_t cells_per_side; /* cell-list cells per side of replica 0            */
+    int32_t block_size;
+    double cell_width;      /* of replica 0                                     */
+} lj_md_info_t;
+mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info);
+
+/* Free the handle and its device memory (NULL-safe). */
+void lj_md_destroy(lj_md* md);
+
+/* ------------------------------------------------------------------------ */
+/* Coarse-graining of one pair of snapshots (Eq.(n_i))                        */
+/* ------------------------------------------------------------------------ */
+
+/* One coarse-graining event between two snapshots of n particles in a box of
+ * side box_l.  pos_prev/pos_cur: device [n][2] float64 wrapped positions at
+ * coarse steps k_prev and k_cur; img_prev/img_cur: device [n][2] int32 image
+ * counts (either may be NULL for zero).  The lattice velocity of particle j is
+ * C_j(k_cur) - C_j(k_prev) with the unwrapped cell C = floor((x + u dx k) *
+ * lx / L) + lx * img; n_i counts it at its destination cell at k_cur.
+ * Outputs (device, any may be NULL except counts):
+ *   counts  int64 [50]   += n_i summed over cells ([49]: overflow)
+ *   moments double [5]   += as in lj_md_cg_attach, d from pos + L * img
+ *   n_event int32 [49][lx][lx] overwritten with n_i(x, t)
+ *   cell_acc int32 [49][lx][lx] += n_i(x, t)
+ * Bitwise equal to the definition for identical inputs (integer counts);
+ * moments use a fixed-order reduction. */
+mdlg_status mdlg_coarse_grain(const mdlg_lattice* lat, double box_l, int64_t n,
+                              const double* pos_prev, const int32_t* img_prev, int64_t k_prev,
+                              const double* pos_cur, const int32_t* img_cur, int64_t k_cur,
+                              int64_t* counts, double* moments, int32_t* n_event, int32_t* cell_acc,
+                              void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Equilibria (host, FP64)                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Measured equilibrium (Eq.(theory_feq)): g_i = f_i^eq / rho with
+ * rho = N / lx^2, i.e. g_i = counts[i] / (n_particles * n_events).
+ * symmetrize = 1 averages g over each |v|^2 shell (the Results section's
+ * symmetrised D2Q25 sets; meaningful for zero mean velocity).
+ * counts: host [50]; g_out: host [49]; overflow_frac: host, may be NULL. */
+mdlg_status mdlg_feq_measured(const int64_t* counts, int64_t n_particles, int64_t n_events,
+                              int32_t symmetrize, double* g_out, double* overflow_frac);
+
+/* Displacement moments from accumulated sums: mu2 = <d^2>, mu4 = <d^4>
+ * (pooled over both axes) and a^2 = mu2 / dx^2 (Eq.(a2_n_ua)).
+ * moments: host [5]; any output may be NULL. */
+mdlg_status mdlg_moments(const double* moments, double dx, double* mu2, double* mu4, double* a2);
+
+/* Average number of collisions lambda of the Poisson-WSG model from the
+ * second and fourth displacement moments (Eq.(lambda_eq)).  With
+ * r = mu4 / (3 mu2^2) the roots are lambda and 1/lambda; branch 2 returns the
+ * larger root (the printed lambda_2, which the paper uses), branch 1 the
+ * smaller.  r <= 1 gives lambda = 0 (single Gaussian); r >= 5/4, beyond the
+ * model's range, gives lambda = 1.  r may be NULL. */
+mdlg_status mdlg_lambda_from_moments(double mu2, double mu4, int32_t branch, double* lambda,
+                                     double* r);
+
+/* Single-Gaussian equilibrium g^G_i = f^eq,G_i / rho (Eq.(feq_prod) and
+ * Eq.(feq_gaussian)); a2 >= 0 in lattice units^2, u host [2] mean
+ * displacement in cells per coarse step (NULL = 0).  g_out host [49]. */
+mdlg_status mdlg_feq_gauss(double a2, const double* u, double* g_out);
+
+/* Poisson-WSG equilibrium (Eq.(f_eq_wsg)): sum over collision counts c of
+ * e^-lambda lambda^c / c! times the product over axes of the Gaussian form
+ * with variance a2 (c+1)/(lambda+1).  The sum is truncated where the
+ * remaining Poisson weight is below 1e-20.  lambda = 0 gives mdlg_feq_gauss. */
+mdlg_status mdlg_feq_wsg(double a2, double lambda, const double* u, double* g_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLG_H */

@@ -1,0 +1,315 @@
+"""MI355X hot path of the molecular dynamics lattice gas (MDLG) method.
+
+Thin Python binding of libmdlg.so (C ABI: include/mdlg.h).  Functions carry
+the C names and only marshal arguments: torch tensors supply device memory
+and the current HIP stream; every step of the computation runs in the
+library's HIP kernels (or, for the closed forms, in its host FP64 code).
+
+Quick use::
+
+    sys = LJSystem(pos0, vel0, box_l=L)              # torch float64 [n, 2] on cuda
+    acc = sys.attach_cg(lx=1024, s_cg=50)             # fused coarse-graining
+    sys.step(20_000)
+    g, ovf = mdlg_feq_measured(acc.counts.cpu().numpy(), n, acc.events)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import Info, LJParams, Lattice, MDLGError
+
+__all__ = [
+    "MDLGError", "LJParams", "Lattice", "LJSystem", "CGAccumulators",
+    "lj_params", "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
+    "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_destroy",
+    "mdlg_coarse_grain", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
+    "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype, n):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def mdlg_version() -> str:
+    return _abi.lib().mdlg_version().decode()
+
+
+def mdlg_velocity_table() -> np.ndarray:
+    out = np.zeros((49, 2), np.int32)
+    _abi.check(_abi.lib().mdlg_velocity_table(out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+# ------------------------------------------------------------------ MD ---
+
+def lj_params(n, box_l, dt=1e-4, rc=2.5, eps=1.0, energy_shift=True, force_bits=64, skin=0.0,
+              rebuild_every=0, block_size=0) -> LJParams:
+    return LJParams(n=int(n), box_l=float(box_l), dt=float(dt), rc=float(rc), eps=float(eps),
+                    energy_shift=1 if energy_shift else 0, force_bits=int(force_bits), skin=float(skin),
+                    rebuild_every=int(rebuild_every), block_size=int(block_size))
+
+
+def lj_md_init(params: LJParams, pos0, vel0, stream=None) -> C.c_void_p:
+    torch = _torch()
+    n = params.n
+    h = C.c_void_p()
+    _abi.check(_abi.lib().lj_md_init(C.byref(h), C.byref(params), _dev(pos0, torch.float64, (n, 2), "pos0"),
+                                     _dev(vel0, torch.float64, (n, 2), "vel0"), _stream(stream)))
+    return h
+
+
+def lj_md_init_batch(params, pos0, vel0, stream=None) -> C.c_void_p:
+    torch = _torch()
+    arr = (LJParams * len(params))(*params)
+    n = sum(p.n for p in params)
+    h = C.c_void_p()
+    _abi.check(_abi.lib().lj_md_init_batch(C.byref(h), len(params), arr, _dev(pos0, torch.float64, (n, 2), "pos0"),
+                                           _dev(vel0, torch.float64, (n, 2), "vel0"), _stream(stream)))
+    return h
+
+
+def lj_md_cg_attach(h, s_cg, lattices, counts, moments, cell_acc=None, stream=None):
+    torch = _torch()
+    lats = (Lattice * len(lattices))(*lattices)
+    _abi.check(_abi.lib().lj_md_cg_attach(h, int(s_cg), lats, _dev(counts, torch.int64, None, "counts"),
+                                          _dev(moments, torch.float64, None, "moments"),
+                                          _dev(cell_acc, torch.int32, None, "cell_acc"), _stream(stream)))
+
+
+def lj_md_cg_detach(h):
+    _abi.check(_abi.lib().lj_md_cg_detach(h))
+
+
+def lj_md_step(h, nsteps, stream=None):
+    _abi.check(_abi.lib().lj_md_step(h, int(nsteps), _stream(stream)))
+
+
+def lj_md_step_timed(h, nsteps, stream=None):
+    """Eager steps with per-launch HIP-event timing.  Returns (avg ms [3], launches [3]) for
+    [plain step kernel, coarse-graining step kernel + reduction, cell-list rebuild]."""
+    ms = np.zeros(3)
+    cnt = np.zeros(3, np.int32)
+    _abi.check(_abi.lib().lj_md_step_timed(h, int(nsteps), ms.ctypes.data_as(C.c_void_p),
+                                           cnt.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return ms, cnt
+
+
+def lj_md_get_state(h, pos=None, vel=None, img=None, stream=None):
+    torch = _torch()
+    _abi.check(_abi.lib().lj_md_get_state(h, _dev(pos, torch.float64, None, "pos"),
+                                          _dev(vel, torch.float64, None, "vel"),
+                                          _dev(img, torch.int32, None, "img"), _stream(stream)))
+
+
+def lj_md_forces(h, force, stream=None):
+    _abi.check(_abi.lib().lj_md_forces(h, _dev(force, _torch().float64, None, "force"), _stream(stream)))
+
+
+def lj_md_energy(h, n_rep=1, stream=None) -> np.ndarray:
+    out = np.zeros((n_rep, 4))
+    _abi.check(_abi.lib().lj_md_energy(h, out.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return out
+
+
+def lj_md_check(h, stream=None):
+    _abi.check(_abi.lib().lj_md_check(h, _stream(stream)))
+
+
+def lj_md_info(h) -> dict:
+    info = Info()
+    _abi.check(_abi.lib().lj_md_info(h, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in Info._fields_}
+
+
+def lj_md_destroy(h):
+    if h:
+        _abi.lib().lj_md_destroy(h)
+
+
+# ------------------------------------------------------- coarse-graining ---
+
+def mdlg_coarse_grain(lx, box_l, pos_prev, pos_cur, counts, moments=None, img_prev=None, img_cur=None,
+                      k_prev=0, k_cur=1, u=(0.0, 0.0), n_event=None, cell_acc=None, stream=None):
+    torch = _torch()
+    n = pos_prev.shape[0]
+    lat = Lattice(lx=int(lx), reserved=0, u=(C.c_double * 2)(float(u[0]), float(u[1])))
+    _abi.check(_abi.lib().mdlg_coarse_grain(
+        C.byref(lat), float(box_l), int(n),
+        _dev(pos_prev, torch.float64, (n, 2), "pos_prev"), _dev(img_prev, torch.int32, (n, 2), "img_prev"),
+        int(k_prev),
+        _dev(pos_cur, torch.float64, (n, 2), "pos_cur"), _dev(img_cur, torch.int32, (n, 2), "img_cur"), int(k_cur),
+        _dev(counts, torch.int64, (50,), "counts"), _dev(moments, torch.float64, (5,), "moments"),
+        _dev(n_event, torch.int32, (49, lx, lx), "n_event"), _dev(cell_acc, torch.int32, (49, lx, lx), "cell_acc"),
+        _stream(stream)))
+
+
+# ------------------------------------------------------------ equilibria ---
+
+def mdlg_feq_measured(counts, n_particles, n_events, symmetrize=False):
+    c = _host(counts, np.int64, 50)
+    g = np.zeros(49)
+    ovf = C.c_double()
+    _abi.check(_abi.lib().mdlg_feq_measured(c.ctypes.data_as(C.c_void_p), int(n_particles), int(n_events),
+                                            1 if symmetrize else 0, g.ctypes.data_as(C.c_void_p), C.byref(ovf)))
+    return g, ovf.value
+
+
+def mdlg_moments(moments, dx):
+    m = _host(moments, np.float64, 5)
+    mu2, mu4, a2 = C.c_double(), C.c_double(), C.c_double()
+    _abi.check(_abi.lib().mdlg_moments(m.ctypes.data_as(C.c_void_p), float(dx), C.byref(mu2), C.byref(mu4),
+                                       C.byref(a2)))
+    return mu2.value, mu4.value, a2.value
+
+
+def mdlg_lambda_from_moments(mu2, mu4, branch=2):
+    lam, r = C.c_double(), C.c_double()
+    _abi.check(_abi.lib().mdlg_lambda_from_moments(float(mu2), float(mu4), int(branch), C.byref(lam), C.byref(r)))
+    return lam.value, r.value
+
+
+def mdlg_feq_gauss(a2, u=(0.0, 0.0)):
+    uu = _host(u, np.float64, 2)
+    g = np.zeros(49)
+    _abi.check(_abi.lib().mdlg_feq_gauss(float(a2), uu.ctypes.data_as(C.c_void_p), g.ctypes.data_as(C.c_void_p)))
+    return g
+
+
+def mdlg_feq_wsg(a2, lam, u=(0.0, 0.0)):
+    uu = _host(u, np.float64, 2)
+    g = np.zeros(49)
+    _abi.check(_abi.lib().mdlg_feq_wsg(float(a2), float(lam), uu.ctypes.data_as(C.c_void_p),
+                                       g.ctypes.data_as(C.c_void_p)))
+    return g
+
+
+# ------------------------------------------------------ convenience class ---
+
+@dataclass
+class CGAccumulators:
+    counts: object    # torch int64 [n_rep, 50]
+    moments: object   # torch float64 [n_rep, 5]
+    cell_acc: object  # torch int32 or None
+    lattices: list
+    s_cg: int
+    system: "LJSystem"
+
+    @property
+    def events(self) -> int:
+        return lj_md_info(self.system.handle)["events_done"]
+
+
+class LJSystem:
+    """Owns one lj_md handle (one system or a batch of replicas)."""
+
+    def __init__(self, pos0, vel0, box_l=None, params=None, stream=None, **kw):
+        if params is None:
+            params = [lj_params(pos0.shape[0], box_l, **kw)]
+        elif isinstance(params, LJParams):
+            params = [params]
+        self.params = list(params)
+        self.n_rep = len(self.params)
+        self.n_total = sum(p.n for p in self.params)
+        self.stream = stream
+        if self.n_rep == 1:
+            self.handle = lj_md_init(self.params[0], pos0, vel0, stream)
+        else:
+            self.handle = lj_md_init_batch(self.params, pos0, vel0, stream)
+        self.cg = None
+
+    def close(self):
+        if self.handle:
+            lj_md_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def attach_cg(self, lx, s_cg, u=(0.0, 0.0), cell_acc=False) -> CGAccumulators:
+        torch = _torch()
+        lxs = list(lx) if hasattr(lx, "__len__") else [lx] * self.n_rep
+        us = list(u) if (hasattr(u, "__len__") and len(u) == self.n_rep and hasattr(u[0], "__len__")) \
+            else [u] * self.n_rep
+        lats = [Lattice(lx=int(l), reserved=0, u=(C.c_double * 2)(float(v[0]), float(v[1])))
+                for l, v in zip(lxs, us)]
+        counts = torch.zeros((self.n_rep, 50), dtype=torch.int64, device="cuda")
+        moments = torch.zeros((self.n_rep, 5), dtype=torch.float64, device="cuda")
+        cacc = None
+        if cell_acc:
+            cacc = torch.zeros(sum(49 * l * l for l in lxs), dtype=torch.int32, device="cuda")
+        lj_md_cg_attach(self.handle, s_cg, lats, counts, moments, cacc, self.stream)
+        self.cg = CGAccumulators(counts, moments, cacc, lats, s_cg, self)
+        return self.cg
+
+    def detach_cg(self):
+        lj_md_cg_detach(self.handle)
+        self.cg = None
+
+    def step(self, nsteps):
+        lj_md_step(self.handle, nsteps, self.stream)
+
+    def step_timed(self, nsteps):
+        return lj_md_step_timed(self.handle, nsteps, self.stream)
+
+    def state(self):
+        torch = _torch()
+        pos = torch.empty((self.n_total, 2), dtype=torch.float64, device="cuda")
+        vel = torch.empty_like(pos)
+        img = torch.empty((self.n_total, 2), dtype=torch.int32, device="cuda")
+        lj_md_get_state(self.handle, pos, vel, img, self.stream)
+        return pos, vel, img
+
+    def forces(self):
+        torch = _torch()
+        f = torch.empty((self.n_total, 2), dtype=torch.float64, device="cuda")
+        lj_md_forces(self.handle, f, self.stream)
+        return f
+
+    def energy(self):
+        return lj_md_energy(self.handle, self.n_rep, self.stream)
+
+    def check(self):
+        lj_md_check(self.handle, self.stream)
+
+    def info(self):
+        return lj_md_info(self.handle)

@@ -1,0 +1,113 @@
+"""ctypes declarations of libmdlg.so (the C ABI in include/mdlg.h).
+
+Loads the in-tree library built by paper_2101_01160_amd/build.py and fails
+loudly when it is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmdlg.so")
+
+MDLG_OK = 0
+STATUS_NAMES = {0: "MDLG_OK", -1: "MDLG_EINVAL", -2: "MDLG_ENOMEM", -3: "MDLG_EHIP", -4: "MDLG_ENONFINITE",
+                -5: "MDLG_ESKIN", -6: "MDLG_ENOTIMPL"}
+
+# every symbol declared in include/mdlg.h
+EXPORTS = [
+    "mdlg_last_error", "mdlg_version", "mdlg_velocity_table",
+    "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
+    "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_destroy",
+    "mdlg_coarse_grain", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
+    "mdlg_feq_gauss", "mdlg_feq_wsg",
+]
+
+
+class LJParams(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("box_l", C.c_double),
+        ("dt", C.c_double),
+        ("rc", C.c_double),
+        ("eps", C.c_double),
+        ("energy_shift", C.c_int32),
+        ("force_bits", C.c_int32),
+        ("skin", C.c_double),
+        ("rebuild_every", C.c_int32),
+        ("block_size", C.c_int32),
+    ]
+
+
+class Lattice(C.Structure):
+    _fields_ = [("lx", C.c_int32), ("reserved", C.c_int32), ("u", C.c_double * 2)]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("n_rep", C.c_int32),
+        ("rebuild_every", C.c_int32),
+        ("n_total", C.c_int64),
+        ("steps_done", C.c_int64),
+        ("events_done", C.c_int64),
+        ("cells_per_side", C.c_int32),
+        ("block_size", C.c_int32),
+        ("cell_width", C.c_double),
+    ]
+
+
+_lib = None
+
+
+class MDLGError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"libmdlg.so is not built ({LIBPATH}); run __graft_entry__.build() or "
+                          "python paper_2101_01160_amd/build.py")
+    L = C.CDLL(LIBPATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "mdlg_last_error": (C.c_char_p, []),
+        "mdlg_version": (C.c_char_p, []),
+        "mdlg_velocity_table": (i32, [vp]),
+        "lj_md_init": (i32, [P(vp), P(LJParams), vp, vp, vp]),
+        "lj_md_init_batch": (i32, [P(vp), i32, P(LJParams), vp, vp, vp]),
+        "lj_md_cg_attach": (i32, [vp, i32, P(Lattice), vp, vp, vp, vp]),
+        "lj_md_cg_detach": (i32, [vp]),
+        "lj_md_step": (i32, [vp, i64, vp]),
+        "lj_md_step_timed": (i32, [vp, i64, vp, vp, vp]),
+        "lj_md_get_state": (i32, [vp, vp, vp, vp, vp]),
+        "lj_md_forces": (i32, [vp, vp, vp]),
+        "lj_md_energy": (i32, [vp, vp, vp]),
+        "lj_md_check": (i32, [vp, vp]),
+        "lj_md_info": (i32, [vp, P(Info)]),
+        "lj_md_destroy": (None, [vp]),
+        "mdlg_coarse_grain": (i32, [P(Lattice), dbl, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]),
+        "mdlg_feq_measured": (i32, [vp, i64, i64, i32, vp, P(dbl)]),
+        "mdlg_moments": (i32, [vp, dbl, P(dbl), P(dbl), P(dbl)]),
+        "mdlg_lambda_from_moments": (i32, [dbl, dbl, i32, P(dbl), P(dbl)]),
+        "mdlg_feq_gauss": (i32, [dbl, vp, vp]),
+        "mdlg_feq_wsg": (i32, [dbl, dbl, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != MDLG_OK:
+        msg = lib().mdlg_last_error().decode(errors="replace")
+        raise MDLGError(status, msg)

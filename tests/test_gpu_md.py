@@ -1,0 +1,227 @@
+"""GPU parity of the MD path (lj_md_*) with the oracle.
+
+Forces, positions and velocities within 1e-10 relative over 100 FP64 steps;
+fused coarse-graining counts bit-exact on the same runs (the two
+trajectories differ only by the order of floating-point sums, far below the
+distance of any particle to a lattice edge at these sizes); conservation
+laws and determinism on the device path itself.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import mdlg_inputs as mi
+from oracle import md as omd
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_system(pos, vel, L, **kw):
+    import paper_2101_01160_amd as m
+    return m.LJSystem(_cuda(pos), _cuda(vel), box_l=L, **kw)
+
+
+def oracle_advanced(n, phi, kT, seed, steps, positions="grid"):
+    pos, vel, L = mi.initial_state(n, phi, kT, seed, positions)
+    if steps:
+        pos, vel, _, _ = omd.md_run(pos, vel, np.zeros((n, 2), np.int64), L, steps)
+    return pos, vel, L
+
+
+@pytest.mark.parametrize("n,phi,kT,bits", [(512, 0.0784, 20.0, 64), (2000, 0.4, 20.0, 64), (3000, 0.2, 1.0, 64),
+                                           (2000, 0.4, 20.0, 32), (3000, 0.2, 1.0, 32)])
+def test_forces_match_brute_force(n, phi, kT, bits):
+    print(f"forces n={n} phi={phi} kT={kT} bits={bits}", flush=True)
+    pos, vel, L = oracle_advanced(n, phi, kT, 7, 300)
+    sysm = gpu_system(pos, vel, L, force_bits=bits)
+    f = _np(sysm.forces())
+    fo, _ = omd.forces(pos, L, method="brute")
+    scale = np.abs(fo).max()
+    tol = 1e-12 if bits == 64 else 2e-5
+    assert np.max(np.abs(f - fo)) <= tol * scale
+    sysm.close()
+
+
+@pytest.mark.parametrize("n,phi,kT,kw", [
+    (512, 0.0784, 20.0, {}),
+    (2000, 0.4, 20.0, {}),
+    (1500, 0.2, 1.0, {"block_size": 64}),
+    (1777, 0.3, 5.0, {"block_size": 512, "rebuild_every": 7}),
+    (700, 0.4, 20.0, {"skin": 0.2, "rebuild_every": 3}),
+])
+def test_100_steps_match_oracle(n, phi, kT, kw):
+    print(f"md100 n={n} phi={phi} kT={kT} {kw}", flush=True)
+    pos0, vel0, L = mi.initial_state(n, phi, kT, 3)
+    sysm = gpu_system(pos0, vel0, L, **kw)
+    sysm.step(37)  # eager steps, then graph-replayed chunks
+    sysm.step(63)
+    pos, vel, img = (_np(t) for t in sysm.state())
+    sysm.check()
+    po, vo, io, _ = omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, 100)
+    assert np.array_equal(img, io)
+    up, uo = pos + L * img, po + L * io
+    assert np.max(np.abs(up - uo)) <= 1e-10 * np.abs(uo).max()
+    assert np.max(np.abs(vel - vo)) <= 1e-10 * np.abs(vo).max()
+    sysm.close()
+
+
+def test_energy_and_momentum_match_oracle_and_are_conserved():
+    n = 2000
+    pos0, vel0, L = mi.initial_state(n, 0.4, 20.0, 5)
+    sysm = gpu_system(pos0, vel0, L)
+    e0 = sysm.energy()[0]
+    o0 = omd.energy(pos0, vel0, L)
+    assert e0[0] == pytest.approx(o0[0], rel=1e-13)
+    assert e0[1] == pytest.approx(o0[1], rel=1e-12, abs=1e-9)
+    sysm.step(2000)
+    e1 = sysm.energy()[0]
+    pos, vel, img = (_np(t) for t in sysm.state())
+    o1 = omd.energy(pos, vel, L)
+    assert e1[0] == pytest.approx(o1[0], rel=1e-12)
+    assert e1[1] == pytest.approx(o1[1], rel=1e-10)
+    assert abs((e1[0] + e1[1]) - (e0[0] + e0[1])) / e0[0] <= 1e-6
+    assert np.max(np.abs(e1[2:] - e0[2:])) <= 1e-10 * math.sqrt(n) * math.sqrt(20.0)
+    sysm.close()
+
+
+def test_grid_start_potential_energy_is_zero():
+    pos0, vel0, L = mi.initial_state(512, 0.0784, 20.0, 0)
+    sysm = gpu_system(pos0, vel0, L)
+    e = sysm.energy()[0]
+    assert e[1] == 0.0
+    assert e[0] == pytest.approx(511 * 20.0, rel=1e-13)
+    sysm.close()
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0), (0.1, -0.05)])
+def test_fused_coarse_graining_matches_oracle(u):
+    # the CPU-sized workload: N = 512, phi = 0.0784, kT = 20, 2000 steps,
+    # 32 x 32 lattice, coarse step 50 MD steps
+    import torch
+    n, steps, lx, s_cg = 512, 2000, 32, 50
+    print(f"fused cg u={u}", flush=True)
+    pos0, vel0, L = mi.initial_state(n, 0.0784, 20.0, 0)
+    sysm = gpu_system(pos0, vel0, L)
+    acc = sysm.attach_cg(lx, s_cg, u=u, cell_acc=True)
+    sysm.step(steps)
+    torch.cuda.synchronize()
+    sysm.check()
+    oacc = omd.CGAccum(lx, cell_acc=True)
+    omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, steps, cg=oacc, s_cg=s_cg, u=u)
+    assert acc.events == oacc.events == steps // s_cg
+    assert np.array_equal(_np(acc.counts)[0], oacc.counts)
+    assert np.array_equal(_np(acc.cell_acc).reshape(49, lx, lx), oacc.cell_acc)
+    mg = _np(acc.moments)[0]
+    assert mg[0] == oacc.moments[0]
+    assert mg[1] == pytest.approx(oacc.moments[1], rel=1e-9)
+    assert mg[2] == pytest.approx(oacc.moments[2], rel=1e-9)
+    sysm.close()
+
+
+def test_batched_replicas_equal_single_runs():
+    import torch
+
+    import paper_2101_01160_amd as m
+    specs = [(600, 0.0784, 20.0, 1), (1500, 0.4, 1.0, 2), (900, 0.2, 5.0, 3)]
+    states = [mi.initial_state(n, phi, kT, seed) for n, phi, kT, seed in specs]
+    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10) for s in states]
+    pos = np.concatenate([s[0] for s in states])
+    vel = np.concatenate([s[1] for s in states])
+    batch = m.LJSystem(_cuda(pos), _cuda(vel), params=params)
+    acc = batch.attach_cg([16, 24, 20], 10)
+    batch.step(60)
+    bp, bv, bi = (_np(t) for t in batch.state())
+    bc = _np(acc.counts)
+    off = 0
+    for r, (p0, v0, L) in enumerate(states):
+        n = p0.shape[0]
+        single = gpu_system(p0, v0, L, rebuild_every=10)
+        sacc = single.attach_cg([16, 24, 20][r], 10)
+        single.step(60)
+        sp, sv, si = (_np(t) for t in single.state())
+        assert np.array_equal(bp[off:off + n], sp)
+        assert np.array_equal(bv[off:off + n], sv)
+        assert np.array_equal(bi[off:off + n], si)
+        assert np.array_equal(bc[r], _np(sacc.counts)[0])
+        single.close()
+        off += n
+    e = batch.energy()
+    assert e.shape == (3, 4)
+    batch.close()
+    torch.cuda.synchronize()
+
+
+def test_runs_are_deterministic():
+    pos0, vel0, L = mi.initial_state(3000, 0.3, 20.0, 9)
+    outs = []
+    for _ in range(2):
+        sysm = gpu_system(pos0, vel0, L, rebuild_every=13)
+        acc = sysm.attach_cg(20, 25)
+        sysm.step(250)
+        outs.append([_np(t) for t in sysm.state()] + [_np(acc.counts), _np(acc.moments)])
+        sysm.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_invalid_inputs_are_rejected():
+    import paper_2101_01160_amd as m
+    pos0, vel0, L = mi.initial_state(64, 0.2, 1.0, 0)
+    with pytest.raises(m.MDLGError):
+        gpu_system(pos0, vel0, 5.0)  # box smaller than 3 cells
+    bad = pos0.copy()
+    bad[3, 0] = L + 1.0
+    with pytest.raises(m.MDLGError):
+        gpu_system(bad, vel0, L)
+    bad = vel0.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(m.MDLGError):
+        gpu_system(pos0, bad, L)
+    with pytest.raises(m.MDLGError):
+        gpu_system(pos0, vel0, L, force_bits=16)
+    sysm = gpu_system(pos0, vel0, L)
+    with pytest.raises(m.MDLGError):
+        sysm.attach_cg(4, 10)  # lattice below 7 cells
+    sysm.close()
+
+
+def test_one_million_particles_sampled():
+    # the benchmark workload: N = 2^20 at phi = 0.0784, kT = 20, 1024^2 lattice,
+    # coarse step 50, default launch configuration
+    import torch
+    n, lx, s_cg = 1 << 20, 1024, 50
+    print("one million: init", flush=True)
+    pos0, vel0, L = mi.initial_state(n, 0.0784, 20.0, 0)
+    sysm = gpu_system(pos0, vel0, L)
+    acc = sysm.attach_cg(lx, s_cg)
+    sysm.step(s_cg)
+    pos, vel, img = (_np(t) for t in sysm.state())
+    f = _np(sysm.forces())
+    sysm.check()
+    # the coarse-graining event equals the definition on the same snapshots
+    co, _, mo = omd.coarse_grain(lx, L, pos0, pos, np.zeros((n, 2), np.int64), img)
+    assert np.array_equal(_np(acc.counts)[0], co)
+    assert int(co.sum()) == n
+    assert _np(acc.moments)[0][1] == pytest.approx(mo[1], rel=1e-10)
+    # forces on the reached configuration equal the oracle's cell-list forces
+    fo, _ = omd.forces(pos, L, method="cells")
+    assert np.max(np.abs(f - fo)) <= 1e-12 * np.abs(fo).max()
+    # one more step from the same state
+    sysm.step(1)
+    p1, v1, i1 = (_np(t) for t in sysm.state())
+    po, vo, io, _ = omd.md_run(pos, vel, img.astype(np.int64), L, 1)
+    assert np.array_equal(i1, io)
+    assert np.max(np.abs((p1 + L * i1) - (po + L * io))) <= 1e-12 * L
+    assert np.max(np.abs(v1 - vo)) <= 1e-12 * np.abs(vo).max()
+    sysm.close()
+    torch.cuda.synchronize()
