@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--force-bits", type=int, default=64, choices=(64, 32))
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--skin", type=float, default=0.0)
+    ap.add_argument("--step-kernel", type=int, default=0)
+    ap.add_argument("--gather-batch", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline-steps", type=int, default=150,
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
@@ -87,7 +89,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     sysm = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L,
-                      force_bits=args.force_bits, block_size=args.block_size, skin=args.skin)
+                      force_bits=args.force_bits, block_size=args.block_size, skin=args.skin,
+                      step_kernel=args.step_kernel, gather_batch=args.gather_batch)
     acc = sysm.attach_cg(lx, s_cg)
     info = sysm.info()
     print(f"# init done: n={n} L={L:.3f} lx={lx} s_cg={s_cg} cells/side={info['cells_per_side']} "

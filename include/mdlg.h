@@ -47,6 +47,7 @@ typedef int32_t mdlg_status;
 #define MDLG_ENONFINITE (-4)  /* non-finite position or velocity on the device   */
 #define MDLG_ESKIN (-5)       /* a particle drifted past the cell-list skin      */
 #define MDLG_ENOTIMPL (-6)    /* feature not available in this build             */
+#define MDLG_ECAPACITY (-7)   /* a neighbour list overflowed its capacity        */
 
 #define MDLG_NQ 49            /* D2Q49 lattice velocities, |v_x|, |v_y| <= 3     */
 #define MDLG_NCOUNTS 50       /* 49 velocities + 1 overflow bin (|v_a| > 3)      */
@@ -84,6 +85,14 @@ typedef struct {
                                from the fastest initial speed (see lj_md_info)    */
     int32_t block_size;     /* threads per block of the step kernel: 0 = 256;
                                64, 128, 256 or 512                                */
+    int32_t step_kernel;    /* 0 = default (3); 1 = one thread per particle with
+                               neighbours gathered from global memory; 2 = tiles
+                               of cells with the neighbour rows staged in LDS;
+                               3 = one thread per particle over a neighbour list
+                               of the pairs within rc + skin, rebuilt with the
+                               cells                                              */
+    int32_t gather_batch;   /* kernel 1: neighbour loads issued per batch, 0 = 8;
+                               4, 8 or 16                                         */
 } lj_params;
 
 typedef struct lj_md lj_md; /* opaque handle; owns all device state */

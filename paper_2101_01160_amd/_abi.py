@@ -13,7 +13,7 @@ LIBPATH = os.path.join(HERE, "libmdlg.so")
 
 MDLG_OK = 0
 STATUS_NAMES = {0: "MDLG_OK", -1: "MDLG_EINVAL", -2: "MDLG_ENOMEM", -3: "MDLG_EHIP", -4: "MDLG_ENONFINITE",
-                -5: "MDLG_ESKIN", -6: "MDLG_ENOTIMPL"}
+                -5: "MDLG_ESKIN", -6: "MDLG_ENOTIMPL", -7: "MDLG_ECAPACITY"}
 
 # every symbol declared in include/mdlg.h
 EXPORTS = [
@@ -37,6 +37,8 @@ class LJParams(C.Structure):
         ("skin", C.c_double),
         ("rebuild_every", C.c_int32),
         ("block_size", C.c_int32),
+        ("step_kernel", C.c_int32),
+        ("gather_batch", C.c_int32),
     ]
 
 

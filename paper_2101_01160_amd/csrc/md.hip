@@ -25,10 +25,13 @@
 // and writes fixed-order moment partials.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
 #include <vector>
+
+#include <hip/hip_ext.h>
 
 #include "mdlg_internal.h"
 
@@ -38,7 +41,7 @@ __constant__ VelLut d_lut = kLut;
 
 constexpr int kPad = 512;  // slot padding of each replica (largest block size)
 
-enum : int { ERR_NONFINITE = 1, ERR_SKIN = 2 };
+enum : int { ERR_NONFINITE = 1, ERR_SKIN = 2, ERR_NLIST = 4 };
 
 struct RepDev {
     double L, halfL, inv_w, w, skin_half;
@@ -46,7 +49,9 @@ struct RepDev {
     float rc2f, eps24f;
     int nc, cell0;  // cells per side; first cell (sentinel of the pad slots at cell0 + nc*nc)
     int slot0, n;   // first slot, real particles
-    int tile0, ntile;  // tiles (blocks) of this replica, in units of the block size
+    int tile0, ntile;  // slot tiles (blocks of the block size) of this replica
+    int ttile0, nttile;  // cell tiles of the step kernel: nc rows x tpr tiles of tw cells
+    int tw, tpr;
     // coarse-graining lattice
     int lx, pad_;
     double inv_lat, sx, sy;  // lx / L; frame drift per coarse step (u * dx)
@@ -67,6 +72,14 @@ struct StepArgs {
     double2* __restrict__ snap;
     unsigned long long* __restrict__ counts;
     double* __restrict__ mpart;
+    int* __restrict__ hpart;
+    const int* __restrict__ ttile_rep;
+    const int* __restrict__ tinfo;
+    int nrep;
+    int nslots;     // total slots: loads of the prologue are clamped below it
+    int stage_max;  // tile kernel: largest staged particle count (<= its LDS capacity)
+    const int* __restrict__ nbl;  // neighbour lists [maxnb][S]
+    const int* __restrict__ nbc;  // neighbour counts [S]
     int* __restrict__ cell_acc;
     const long long* __restrict__ event_k;
     // observation
@@ -161,100 +174,436 @@ __device__ __forceinline__ void pair_forces(const double2* __restrict__ pin, con
     pe = ae;
 }
 
-// Coarse-graining epilogue of one step kernel block (all threads take part).
-template <int BS>
-__device__ __forceinline__ void cg_epilogue(const StepArgs& a, const RepDev& R, int r, int tile, int s,
-                                            bool act, double2 p) {
-    __shared__ int hist[MDLG_NCOUNTS];
-    __shared__ double red[BS / 64][4];
-    const int tid = threadIdx.x;
-    if (tid < MDLG_NCOUNTS) hist[tid] = 0;
-    __syncthreads();
+// Lattice velocity index (D2Q49, 49 = overflow) and destination cell of one
+// particle between its snapshot sp (coarse step k-1) and position p (step k).
+__device__ __forceinline__ int cg_index(const RepDev& R, long long k, double2 p, double2 sp, long long& cell) {
+    const long long lx = R.lx;
+    const long long qxc = lattice_q(p.x, frame_shift(R.sx, k), R.inv_lat);
+    const long long qyc = lattice_q(p.y, frame_shift(R.sy, k), R.inv_lat);
+    const long long qxp = lattice_q(sp.x, frame_shift(R.sx, k - 1), R.inv_lat);
+    const long long qyp = lattice_q(sp.y, frame_shift(R.sy, k - 1), R.inv_lat);
+    long long vx = qxc - qxp, vy = qyc - qyp;
+    // lattice minimum image: a particle that crossed the box edge
+    if (2 * vx > lx) vx -= lx; else if (2 * vx < -lx) vx += lx;
+    if (2 * vy > lx) vy -= lx; else if (2 * vy < -lx) vy += lx;
     int idx = MDLG_NQ;
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
-    if (act) {
-        const long long k = *a.event_k;
-        const double2 sp = a.snap[s];
-        const int lx = R.lx;
-        const long long qxc = lattice_q(p.x, frame_shift(R.sx, k), R.inv_lat);
-        const long long qyc = lattice_q(p.y, frame_shift(R.sy, k), R.inv_lat);
-        const long long qxp = lattice_q(sp.x, frame_shift(R.sx, k - 1), R.inv_lat);
-        const long long qyp = lattice_q(sp.y, frame_shift(R.sy, k - 1), R.inv_lat);
-        long long vx = qxc - qxp, vy = qyc - qyp;
-        // lattice minimum image: a particle that crossed the box edge
-        if (2 * vx > lx) vx -= lx; else if (2 * vx < -lx) vx += lx;
-        if (2 * vy > lx) vy -= lx; else if (2 * vy < -lx) vy += lx;
-        if (vx >= -3 && vx <= 3 && vy >= -3 && vy <= 3) idx = d_lut.idx[(vy + 3) * 7 + (vx + 3)];
-        if (idx < MDLG_NQ && a.cell_acc) {
-            long long cxm = qxc, cym = qyc;
-            if (cxm < 0 || cxm >= lx) { cxm %= lx; if (cxm < 0) cxm += lx; }
-            if (cym < 0 || cym >= lx) { cym %= lx; if (cym < 0) cym += lx; }
-            atomicAdd(&a.cell_acc[R.cacc0 + ((long long)idx * lx + cym) * lx + cxm], 1);
-        }
-        const double dx = min_image(p.x - sp.x, R.L, R.halfL);
-        const double dy = min_image(p.y - sp.y, R.L, R.halfL);
-        const double dx2 = dx * dx, dy2 = dy * dy;
-        m0 = dx2 + dy2;
-        m1 = dx2 * dx2 + dy2 * dy2;
-        m2 = dx;
-        m3 = dy;
-        a.snap[s] = p;
-    }
-    const unsigned long long rest = __ballot(act && idx == 0);
-    if ((tid & 63) == 0 && rest) atomicAdd(&hist[0], (int)__popcll(rest));
-    if (act && idx != 0) atomicAdd(&hist[idx], 1);
-    m0 = wave_sum(m0);
-    m1 = wave_sum(m1);
-    m2 = wave_sum(m2);
-    m3 = wave_sum(m3);
-    if ((tid & 63) == 0) {
-        red[tid >> 6][0] = m0;
-        red[tid >> 6][1] = m1;
-        red[tid >> 6][2] = m2;
-        red[tid >> 6][3] = m3;
-    }
-    __syncthreads();
-    if (tid < MDLG_NCOUNTS && hist[tid])
-        atomicAdd(&a.counts[(long long)r * MDLG_NCOUNTS + tid], (unsigned long long)hist[tid]);
-    if (tid < 4) {
-        double t = 0.0;
-        for (int w = 0; w < BS / 64; ++w) t += red[w][tid];
-        a.mpart[(long long)tile * MDLG_NMOMENTS + 1 + tid] = t;
-    }
-    if (tid == 0) {
-        int nact = R.n - (tile * BS - R.slot0);
-        nact = nact < 0 ? 0 : (nact > BS ? BS : nact);
-        a.mpart[(long long)tile * MDLG_NMOMENTS] = 2.0 * (double)nact;
+    if (vx >= -3 && vx <= 3 && vy >= -3 && vy <= 3) idx = d_lut.idx[(vy + 3) * 7 + (vx + 3)];
+    long long cxm = qxc, cym = qyc;
+    if (cxm < 0 || cxm >= lx) { cxm %= lx; if (cxm < 0) cxm += lx; }
+    if (cym < 0 || cym >= lx) { cym %= lx; if (cym < 0) cym += lx; }
+    cell = cym * lx + cxm;
+    return idx;
+}
+
+// Per-tile table of the step kernel's LDS staging, rebuilt with the cell
+// list: for each of the three staged rows (row-1, row, row+1) the global slot
+// start and count of its three pieces: the left halo cell, the tile's own
+// cells x0..x1-1, and the right halo cell.
+constexpr int kTileInfo = 18;
+
+__global__ void k_tile_info(const int* __restrict__ cs, const RepDev* __restrict__ reps,
+                            const int* __restrict__ ttile_rep, int TT, int* __restrict__ tinfo) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= TT) return;
+    const RepDev& R = reps[ttile_rep[t]];
+    const int nc = R.nc;
+    const int lt = t - R.ttile0;
+    const int row = lt / R.tpr;
+    const int x0 = (lt % R.tpr) * R.tw;
+    const int x1 = min(nc, x0 + R.tw);
+    const int xa = x0 > 0 ? x0 - 1 : nc - 1;
+    const int xc = x1 < nc ? x1 : 0;
+    for (int rr = 0; rr < 3; ++rr) {
+        int rw = row + rr - 1;
+        rw = rw < 0 ? rw + nc : (rw >= nc ? rw - nc : rw);
+        const int base = R.cell0 + rw * nc;
+        int* o = tinfo + (long long)t * kTileInfo + rr * 6;
+        o[0] = cs[base + xa];
+        o[1] = cs[base + xa + 1] - o[0];
+        o[2] = cs[base + x0];
+        o[3] = cs[base + x1] - o[2];
+        o[4] = cs[base + xc];
+        o[5] = cs[base + xc + 1] - o[4];
     }
 }
 
-// One velocity-Verlet step (FIRST: the stored velocity is a full-step one).
+// One velocity-Verlet step over one tile of cells (FIRST: the stored velocity
+// is a full-step one; CG: this step ends a coarse step).
+//
+// A tile is `tw` consecutive cells of one cell row.  The block stages the
+// particles of the three rows around it (cells x0-1 .. x1 of rows row-1 ..
+// row+1, periodic) into LDS with coalesced loads, shifting halo copies that
+// lie across the box edge by -L or +L so that plain differences are minimum-
+// image separations.  Each thread then takes one particle of the tile's own
+// cells and sums its pair forces over the 3 x 3 cells around the cell it was
+// sorted into.  LDS layout per staged row: left halo cell, the tile's cells,
+// right halo cell; lcs[row][c] is the LDS offset of cell c of that row (c = 0:
+// left halo).  All global loads of the prologue are issued before the first
+// LDS write.  A tile whose rows do not fit in LDS reads them from global
+// memory instead (same loop, minimum image applied).
 template <int BS, bool F32, bool FIRST, bool CG>
-__global__ __launch_bounds__(BS) void k_step(StepArgs a) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int r = a.tile_rep[tile];
+__global__ __launch_bounds__(BS) void k_step_tile(StepArgs a) {
+    constexpr int MAXP = 4 * BS;
+    constexpr int MAXTW = 2 * BS;
+    constexpr int NLCS = (3 * (MAXTW + 1) + BS - 1) / BS;
+    __shared__ double2 lp[MAXP];
+    __shared__ int lcs[3][MAXTW + 3];
+    __shared__ int hist[MDLG_NCOUNTS];
+    __shared__ double red[BS / 64][4];
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ttile_rep[t]);
     const RepDev& R = a.reps[r];
-    const int s = tile * BS + threadIdx.x;
-    const bool act = s - R.slot0 < R.n;
-    double2 pn = make_double2(0.0, 0.0);
+    const int nc = R.nc;
+    const double L = R.L, halfL = R.halfL, rc2 = R.rc2, eps24 = R.eps24;
+    const float rc2f = R.rc2f, eps24f = R.eps24f;
+    const int lt = t - R.ttile0;
+    const int row = lt / R.tpr;
+    const int x0 = (lt % R.tpr) * R.tw;
+    const int x1 = min(nc, x0 + R.tw);
+    const int tw = x1 - x0;
+    const int tid = threadIdx.x;
+    const int* ti = a.tinfo + (long long)t * kTileInfo;
+    int gA[3], nA[3], gB[3], nB[3], gC[3], nC[3], off[4];
+    off[0] = 0;
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr) {
+        gA[rr] = ti[rr * 6 + 0];
+        nA[rr] = ti[rr * 6 + 1];
+        gB[rr] = ti[rr * 6 + 2];
+        nB[rr] = ti[rr * 6 + 3];
+        gC[rr] = ti[rr * 6 + 4];
+        nC[rr] = ti[rr * 6 + 5];
+        off[rr + 1] = off[rr] + nA[rr] + nB[rr] + nC[rr];
+    }
+    const int total = off[3];
+    const bool staged = total <= MAXP && total <= a.stage_max;
+    const int nown = nB[1];
+    const int lown = off[1] + nA[1];
+    // periodic shifts of the halo copies
+    const double sxa = x0 == 0 ? -L : 0.0, sxc = x1 == nc ? L : 0.0;
+    const double sy0 = row == 0 ? -L : 0.0, sy2 = row == nc - 1 ? L : 0.0;
+
+    // ---- prologue: every global load first ----
+    const int nl = 3 * (tw + 1);
+    int cv[NLCS];
+#pragma unroll
+    for (int u = 0; u < NLCS; ++u) {
+        const int i = tid + u * BS;
+        const int ii = i < nl ? i : 0;
+        const int rr = ii / (tw + 1), j = ii - rr * (tw + 1);
+        int rw = row + rr - 1;
+        rw = rw < 0 ? rw + nc : (rw >= nc ? rw - nc : rw);
+        cv[u] = a.cs[R.cell0 + rw * nc + x0 + j];
+    }
+    double2 sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = tid + u * BS;
+        int g = min(gB[1], a.nslots - 1);
+        if (staged && i < total) {
+            const int rr = i < off[1] ? 0 : (i < off[2] ? 1 : 2);
+            const int q = i - (rr == 0 ? off[0] : (rr == 1 ? off[1] : off[2]));
+            const int na = rr == 0 ? nA[0] : (rr == 1 ? nA[1] : nA[2]);
+            const int nb = rr == 0 ? nB[0] : (rr == 1 ? nB[1] : nB[2]);
+            const int ga = rr == 0 ? gA[0] : (rr == 1 ? gA[1] : gA[2]);
+            const int gb = rr == 0 ? gB[0] : (rr == 1 ? gB[1] : gB[2]);
+            const int gc = rr == 0 ? gC[0] : (rr == 1 ? gC[1] : gC[2]);
+            g = q < na ? ga + q : (q < na + nb ? gb + q - na : gc + q - na - nb);
+        }
+        sv[u] = a.pin[g];
+    }
+    const int s0 = min(gB[1] + (tid < nown ? tid : 0), a.nslots - 1);
+    double2 v0 = a.vel[s0];
+    double2 sp0 = make_double2(0.0, 0.0);
+    if (CG) sp0 = a.snap[s0];
+
+    // ---- LDS writes ----
+#pragma unroll
+    for (int u = 0; u < NLCS; ++u) {
+        const int i = tid + u * BS;
+        if (i < nl) {
+            const int rr = i / (tw + 1), j = i - rr * (tw + 1);
+            const int o = rr == 0 ? off[0] : (rr == 1 ? off[1] : off[2]);
+            const int na = rr == 0 ? nA[0] : (rr == 1 ? nA[1] : nA[2]);
+            const int gb = rr == 0 ? gB[0] : (rr == 1 ? gB[1] : gB[2]);
+            lcs[rr][1 + j] = o + na + (cv[u] - gb);
+        }
+    }
+    if (tid < 3) {
+        lcs[tid][0] = tid == 0 ? off[0] : (tid == 1 ? off[1] : off[2]);
+        lcs[tid][tw + 2] = tid == 0 ? off[1] : (tid == 1 ? off[2] : off[3]);
+    }
+    if (staged) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = tid + u * BS;
+            if (i < total) {
+                const int rr = i < off[1] ? 0 : (i < off[2] ? 1 : 2);
+                const int q = i - (rr == 0 ? off[0] : (rr == 1 ? off[1] : off[2]));
+                const int na = rr == 0 ? nA[0] : (rr == 1 ? nA[1] : nA[2]);
+                const int nb = rr == 0 ? nB[0] : (rr == 1 ? nB[1] : nB[2]);
+                double2 w = sv[u];
+                w.x += q < na ? sxa : (q < na + nb ? 0.0 : sxc);
+                w.y += rr == 0 ? sy0 : (rr == 2 ? sy2 : 0.0);
+                lp[i] = w;
+            }
+        }
+    }
+    if (CG && tid < MDLG_NCOUNTS) hist[tid] = 0;
+    __syncthreads();
+
+    long long kcg = 0;
+    if (CG) kcg = *a.event_k;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    for (int i0 = 0; i0 < nown; i0 += BS) {
+        const int i = i0 + tid;
+        const bool act = i < nown;
+        const int l = lown + i;
+        const int s = gB[1] + i;
+        int idx = MDLG_NQ;
+        if (act) {
+            const double2 p = staged ? lp[l] : a.pin[s];
+            // the cell this particle was sorted into: largest j with lcs[1][1 + j] <= l
+            int lo = 0, hi = tw;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (lcs[1][1 + mid] <= l) lo = mid; else hi = mid;
+            }
+            const int j = lo;
+            double ax = 0.0, ay = 0.0;
+            float bx = 0.0f, by = 0.0f;
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+                const int k0 = lcs[rr][j], k1 = lcs[rr][j + 3];
+                for (int k = k0; k < k1; ++k) {
+                    if (rr == 1 && k == l) continue;
+                    double dx, dy;
+                    if (staged) {
+                        const double2 q = lp[k];
+                        dx = p.x - q.x;
+                        dy = p.y - q.y;
+                    } else {
+                        const int o = rr == 0 ? off[0] : (rr == 1 ? off[1] : off[2]);
+                        const int na = rr == 0 ? nA[0] : (rr == 1 ? nA[1] : nA[2]);
+                        const int nb = rr == 0 ? nB[0] : (rr == 1 ? nB[1] : nB[2]);
+                        const int ga = rr == 0 ? gA[0] : (rr == 1 ? gA[1] : gA[2]);
+                        const int gb = rr == 0 ? gB[0] : (rr == 1 ? gB[1] : gB[2]);
+                        const int gc = rr == 0 ? gC[0] : (rr == 1 ? gC[1] : gC[2]);
+                        const int qq = k - o;
+                        const int g = qq < na ? ga + qq : (qq < na + nb ? gb + qq - na : gc + qq - na - nb);
+                        const double2 q = a.pin[g];
+                        dx = min_image(p.x - q.x, L, halfL);
+                        dy = min_image(p.y - q.y, L, halfL);
+                    }
+                    if (F32) {
+                        const float fdx = (float)dx, fdy = (float)dy;
+                        const float r2 = fdx * fdx + fdy * fdy;
+                        if (r2 < rc2f) {
+                            const float ir2 = 1.0f / r2;
+                            const float ir6 = ir2 * ir2 * ir2;
+                            const float fr = eps24f * ir6 * (2.0f * ir6 - 1.0f) * ir2;
+                            bx += fr * fdx;
+                            by += fr * fdy;
+                        }
+                    } else {
+                        const double r2 = dx * dx + dy * dy;
+                        if (r2 < rc2) {
+                            const double ir2 = 1.0 / r2;
+                            const double ir6 = ir2 * ir2 * ir2;
+                            const double fr = eps24 * ir6 * (2.0 * ir6 - 1.0) * ir2;
+                            ax += fr * dx;
+                            ay += fr * dy;
+                        }
+                    }
+                }
+            }
+            const double fx = F32 ? (double)bx : ax;
+            const double fy = F32 ? (double)by : ay;
+            double2 v = i0 == 0 ? v0 : a.vel[s];
+            if (!FIRST) {
+                v.x = v.x + a.hdt * fx;
+                v.y = v.y + a.hdt * fy;
+            }
+            v.x = v.x + a.hdt * fx;
+            v.y = v.y + a.hdt * fy;
+            double2 pn;
+            pn.x = p.x + a.dt * v.x;
+            pn.y = p.y + a.dt * v.y;
+            int wx = 0, wy = 0;
+            if (pn.x >= L) { pn.x -= L; wx = 1; }
+            else if (pn.x < 0.0) { pn.x += L; wx = -1; if (pn.x >= L) { pn.x = 0.0; wx = 0; } }
+            if (pn.y >= L) { pn.y -= L; wy = 1; }
+            else if (pn.y < 0.0) { pn.y += L; wy = -1; if (pn.y >= L) { pn.y = 0.0; wy = 0; } }
+            if (wx | wy) {
+                int2 im = a.img[s];
+                im.x += wx;
+                im.y += wy;
+                a.img[s] = im;
+            }
+            if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
+            a.pout[s] = pn;
+            a.vel[s] = v;
+            if (CG) {
+                const double2 sp = i0 == 0 ? sp0 : a.snap[s];
+                long long cell;
+                idx = cg_index(R, kcg, pn, sp, cell);
+                if (idx < MDLG_NQ && a.cell_acc)
+                    atomicAdd(&a.cell_acc[R.cacc0 + (long long)idx * R.lx * R.lx + cell], 1);
+                const double dx = min_image(pn.x - sp.x, L, halfL);
+                const double dy = min_image(pn.y - sp.y, L, halfL);
+                const double dx2 = dx * dx, dy2 = dy * dy;
+                m0 += dx2 + dy2;
+                m1 += dx2 * dx2 + dy2 * dy2;
+                m2 += dx;
+                m3 += dy;
+                a.snap[s] = pn;
+            }
+        }
+        if (CG) {
+            // most particles keep their cell over a coarse step: count v = 0 with one ballot per wave
+            const unsigned long long rest = __ballot(act && idx == 0);
+            if ((tid & 63) == 0 && rest) atomicAdd(&hist[0], (int)__popcll(rest));
+            if (act && idx != 0) atomicAdd(&hist[idx], 1);
+        }
+    }
+    if (CG) {
+        m0 = wave_sum(m0);
+        m1 = wave_sum(m1);
+        m2 = wave_sum(m2);
+        m3 = wave_sum(m3);
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = m0;
+            red[tid >> 6][1] = m1;
+            red[tid >> 6][2] = m2;
+            red[tid >> 6][3] = m3;
+        }
+        __syncthreads();
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)t * MDLG_NCOUNTS + tid] = hist[tid];
+        if (tid < 4) {
+            double sum = 0.0;
+            for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
+            a.mpart[(long long)t * MDLG_NMOMENTS + 1 + tid] = sum;
+        }
+        if (tid == 0) a.mpart[(long long)t * MDLG_NMOMENTS] = 2.0 * (double)nown;
+    }
+}
+
+// One velocity-Verlet step, one thread per slot, neighbours gathered from
+// global memory (FIRST: the stored velocity is a full-step one; CG: this step
+// ends a coarse step).
+//
+// Latency, not bandwidth, bounds this kernel at low density, so every wave
+// keeps its chain of dependent memory round trips short: position and
+// velocity are loaded together; the nine cell bounds of the 3 x 3 stencil
+// (three contiguous row ranges, split at the periodic edge) together; then
+// the candidate neighbours in batches of U independent loads.
+template <int BS, bool F32, bool FIRST, bool CG, int U>
+__global__ __launch_bounds__(BS) void k_step_gather(StepArgs a) {
+    __shared__ int hist[MDLG_NCOUNTS];
+    __shared__ double red[BS / 64][4];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = __builtin_amdgcn_readfirstlane(a.tile_rep[tile]);
+    const RepDev& R = a.reps[r];
+    const double L = R.L, halfL = R.halfL, rc2 = R.rc2, eps24 = R.eps24, inv_w = R.inv_w;
+    const float rc2f = R.rc2f, eps24f = R.eps24f;
+    const int nc = R.nc, cell0 = R.cell0;
+    const int tid = threadIdx.x;
+    const int s = tile * BS + tid;
+    const int nact_blk = min(BS, max(0, R.n - (tile * BS - R.slot0)));
+    const bool act = tid < nact_blk;
+    if (CG && tid < MDLG_NCOUNTS) hist[tid] = 0;
+
+    const int sl = act ? s : tile * BS;  // a valid slot for the inactive lanes' loads
+    const double2 p = a.pin[sl];
+    double2 v = a.vel[sl];
+    const int cx = cell_coord(p.x, inv_w, nc);
+    const int cy = cell_coord(p.y, inv_w, nc);
+    // stencil ranges: per row either one range (cells cx-1..cx+1) or two at the edge
+    int ra[3], rb[3], na[3], nb[3];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr) {
+        int rw = cy + rr - 1;
+        rw = rw < 0 ? rw + nc : (rw >= nc ? rw - nc : rw);
+        const int base = cell0 + rw * nc;
+        const int xl = cx > 0 ? cx - 1 : 0;
+        const int xr = cx < nc - 1 ? cx + 2 : nc;
+        const int c0 = a.cs[base + xl], c1 = a.cs[base + xr];
+        // the wrapped cell (if any): nc - 1 when cx == 0, 0 when cx == nc - 1
+        const int xw = cx == 0 ? nc - 1 : 0;
+        const bool wrap = (cx == 0) || (cx == nc - 1);
+        const int w0 = wrap ? a.cs[base + xw] : 0, w1 = wrap ? a.cs[base + xw + 1] : 0;
+        ra[rr] = c0;
+        na[rr] = c1 - c0;
+        rb[rr] = w0;
+        nb[rr] = w1 - w0;
+    }
+    const int e0 = na[0], e1 = e0 + nb[0], e2 = e1 + na[1], e3 = e2 + nb[1], e4 = e3 + na[2], e5 = e4 + nb[2];
+    const int tot = act ? e5 : 0;
+    double ax = 0.0, ay = 0.0;
+    float bx = 0.0f, by = 0.0f;
+    for (int t0 = 0; t0 < tot; t0 += U) {
+        double2 q[U];
+        int kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u;
+            int k = t < e0 ? ra[0] + t
+                  : t < e1 ? rb[0] + (t - e0)
+                  : t < e2 ? ra[1] + (t - e1)
+                  : t < e3 ? rb[1] + (t - e2)
+                  : t < e4 ? ra[2] + (t - e3)
+                           : rb[2] + (t - e4);
+            k = t < tot ? k : sl;
+            kk[u] = t < tot ? k : -1;
+            q[u] = a.pin[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (kk[u] < 0 || kk[u] == s) continue;
+            const double dx = min_image(p.x - q[u].x, L, halfL);
+            const double dy = min_image(p.y - q[u].y, L, halfL);
+            if (F32) {
+                const float fdx = (float)dx, fdy = (float)dy;
+                const float r2 = fdx * fdx + fdy * fdy;
+                if (r2 < rc2f) {
+                    const float ir2 = 1.0f / r2;
+                    const float ir6 = ir2 * ir2 * ir2;
+                    const float fr = eps24f * ir6 * (2.0f * ir6 - 1.0f) * ir2;
+                    bx += fr * fdx;
+                    by += fr * fdy;
+                }
+            } else {
+                const double r2 = dx * dx + dy * dy;
+                if (r2 < rc2) {
+                    const double ir2 = 1.0 / r2;
+                    const double ir6 = ir2 * ir2 * ir2;
+                    const double fr = eps24 * ir6 * (2.0 * ir6 - 1.0) * ir2;
+                    ax += fr * dx;
+                    ay += fr * dy;
+                }
+            }
+        }
+    }
+    int idx = MDLG_NQ;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (act) {
-        const double2 p = a.pin[s];
-        double fx, fy, pe;
-        pair_forces<F32, false>(a.pin, a.cs, R, s, p.x, p.y, fx, fy, pe);
-        double2 v = a.vel[s];
+        const double fx = F32 ? (double)bx : ax;
+        const double fy = F32 ? (double)by : ay;
         if (!FIRST) {
             v.x = v.x + a.hdt * fx;
             v.y = v.y + a.hdt * fy;
         }
         v.x = v.x + a.hdt * fx;
         v.y = v.y + a.hdt * fy;
+        double2 pn;
         pn.x = p.x + a.dt * v.x;
         pn.y = p.y + a.dt * v.y;
         int wx = 0, wy = 0;
-        if (pn.x >= R.L) { pn.x -= R.L; wx = 1; }
-        else if (pn.x < 0.0) { pn.x += R.L; wx = -1; if (pn.x >= R.L) { pn.x = 0.0; wx = 0; } }
-        if (pn.y >= R.L) { pn.y -= R.L; wy = 1; }
-        else if (pn.y < 0.0) { pn.y += R.L; wy = -1; if (pn.y >= R.L) { pn.y = 0.0; wy = 0; } }
+        if (pn.x >= L) { pn.x -= L; wx = 1; }
+        else if (pn.x < 0.0) { pn.x += L; wx = -1; if (pn.x >= L) { pn.x = 0.0; wx = 0; } }
+        if (pn.y >= L) { pn.y -= L; wy = 1; }
+        else if (pn.y < 0.0) { pn.y += L; wy = -1; if (pn.y >= L) { pn.y = 0.0; wy = 0; } }
         if (wx | wy) {
             int2 im = a.img[s];
             im.x += wx;
@@ -264,8 +613,282 @@ __global__ __launch_bounds__(BS) void k_step(StepArgs a) {
         if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
         a.pout[s] = pn;
         a.vel[s] = v;
+        if (CG) {
+            const double2 sp = a.snap[s];
+            long long cell;
+            idx = cg_index(R, *a.event_k, pn, sp, cell);
+            if (idx < MDLG_NQ && a.cell_acc) atomicAdd(&a.cell_acc[R.cacc0 + (long long)idx * R.lx * R.lx + cell], 1);
+            const double dx = min_image(pn.x - sp.x, L, halfL);
+            const double dy = min_image(pn.y - sp.y, L, halfL);
+            const double dx2 = dx * dx, dy2 = dy * dy;
+            m0 = dx2 + dy2;
+            m1 = dx2 * dx2 + dy2 * dy2;
+            m2 = dx;
+            m3 = dy;
+            a.snap[s] = pn;
+        }
     }
-    if (CG) cg_epilogue<BS>(a, R, r, tile, s, act, pn);
+    if (CG) {
+        __syncthreads();  // hist cleared
+        const unsigned long long rest = __ballot(act && idx == 0);
+        if ((tid & 63) == 0 && rest) atomicAdd(&hist[0], (int)__popcll(rest));
+        if (act && idx != 0) atomicAdd(&hist[idx], 1);
+        m0 = wave_sum(m0);
+        m1 = wave_sum(m1);
+        m2 = wave_sum(m2);
+        m3 = wave_sum(m3);
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = m0;
+            red[tid >> 6][1] = m1;
+            red[tid >> 6][2] = m2;
+            red[tid >> 6][3] = m3;
+        }
+        __syncthreads();
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tile * MDLG_NCOUNTS + tid] = hist[tid];
+        if (tid < 4) {
+            double sum = 0.0;
+            for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
+            a.mpart[(long long)tile * MDLG_NMOMENTS + 1 + tid] = sum;
+        }
+        if (tid == 0) a.mpart[(long long)tile * MDLG_NMOMENTS] = 2.0 * (double)nact_blk;
+    }
+}
+
+// Minimum-image separation through the nearest whole number of boxes:
+// d - L rint(d / L), rounded once; equal to the compare-and-select form for
+// |d| < L.
+__device__ __forceinline__ double min_image_rint(double d, double L, double invL) {
+    return fma(-L, rint(d * invL), d);
+}
+
+// 1/x for x > 0 from the hardware reciprocal and two Newton steps (the
+// relative error of the result is a few units in the last place).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Neighbour lists: for every slot, the slots within rc + skin (the cell width)
+// of it, found through the 3 x 3 cells right after the cell-list rebuild.
+// Layout nbl[j * S + s] (consecutive slots consecutive in memory for each j).
+// Also records the positions of the build for the next drift check.
+__global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__ pos, const int* __restrict__ cs,
+                                                     const RepDev* __restrict__ reps, const int* __restrict__ tile_rep,
+                                                     int BSt, int S, int maxnb, int* __restrict__ nbl,
+                                                     int* __restrict__ nbc, double2* __restrict__ pref, int* err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const RepDev& R = reps[tile_rep[s / BSt]];
+    if (s - R.slot0 >= R.n) {
+        nbc[s] = 0;
+        return;
+    }
+    const double2 p = pos[s];
+    pref[s] = p;
+    const int nc = R.nc;
+    const double invL = 1.0 / R.L;
+    const double rl2 = R.w * R.w;
+    const int cx = cell_coord(p.x, R.inv_w, nc);
+    const int cy = cell_coord(p.y, R.inv_w, nc);
+    int cnt = 0;
+    for (int oy = -1; oy <= 1; ++oy) {
+        int rw = cy + oy;
+        rw = rw < 0 ? rw + nc : (rw >= nc ? rw - nc : rw);
+        for (int ox = -1; ox <= 1; ++ox) {
+            int cl = cx + ox;
+            cl = cl < 0 ? cl + nc : (cl >= nc ? cl - nc : cl);
+            const int c = R.cell0 + rw * nc + cl;
+            for (int k = cs[c]; k < cs[c + 1]; ++k) {
+                if (k == s) continue;
+                const double2 q = pos[k];
+                const double dx = min_image_rint(p.x - q.x, R.L, invL);
+                const double dy = min_image_rint(p.y - q.y, R.L, invL);
+                if (dx * dx + dy * dy < rl2) {
+                    if (cnt < maxnb) nbl[(long long)cnt * S + s] = k;
+                    ++cnt;
+                }
+            }
+        }
+    }
+    if (cnt > maxnb) {
+        atomicOr(err, ERR_NLIST);
+        cnt = maxnb;
+    }
+    nbc[s] = cnt;
+}
+
+// One velocity-Verlet step, one thread per slot, pair forces over the slot's
+// neighbour list (FIRST: the stored velocity is a full-step one; CG: this step
+// ends a coarse step).  Per neighbour: one coalesced index load, one position
+// gather, the minimum image through rint, and the pair force with the
+// reciprocal from the hardware estimate refined by Newton steps.
+template <int BS, bool F32, bool FIRST, bool CG>
+__global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
+    __shared__ int hist[MDLG_NCOUNTS];
+    __shared__ double red[BS / 64][4];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.tile_rep[tile]);
+    const RepDev& R = a.reps[r];
+    const double L = R.L, halfL = R.halfL, rc2 = R.rc2, eps24 = R.eps24;
+    const double invL = 1.0 / L;
+    const float rc2f = R.rc2f, eps24f = R.eps24f;
+    const int tid = threadIdx.x;
+    const int s = tile * BS + tid;
+    const int S = a.nslots;
+    const int nact_blk = min(BS, max(0, R.n - (tile * BS - R.slot0)));
+    const bool act = tid < nact_blk;
+    if (CG && tid < MDLG_NCOUNTS) hist[tid] = 0;
+
+    const double2 p = a.pin[s];
+    double2 v = a.vel[s];
+    const int nn = act ? a.nbc[s] : 0;
+    double ax = 0.0, ay = 0.0;
+    float bx = 0.0f, by = 0.0f;
+    for (int j = 0; j < nn; ++j) {
+        const int k = a.nbl[(long long)j * S + s];
+        const double2 q = a.pin[k];
+        const double dx = min_image_rint(p.x - q.x, L, invL);
+        const double dy = min_image_rint(p.y - q.y, L, invL);
+        if (F32) {
+            const float fdx = (float)dx, fdy = (float)dy;
+            const float r2 = fdx * fdx + fdy * fdy;
+            if (r2 < rc2f) {
+                const float ir2 = __builtin_amdgcn_rcpf(r2);
+                const float ir2n = ir2 * (2.0f - r2 * ir2);
+                const float ir6 = ir2n * ir2n * ir2n;
+                const float fr = eps24f * ir6 * (2.0f * ir6 - 1.0f) * ir2n;
+                bx += fr * fdx;
+                by += fr * fdy;
+            }
+        } else {
+            const double r2 = dx * dx + dy * dy;
+            if (r2 < rc2) {
+                const double ir2 = recip(r2);
+                const double ir6 = ir2 * ir2 * ir2;
+                const double fr = eps24 * ir6 * (2.0 * ir6 - 1.0) * ir2;
+                ax += fr * dx;
+                ay += fr * dy;
+            }
+        }
+    }
+    int idx = MDLG_NQ;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    if (act) {
+        const double fx = F32 ? (double)bx : ax;
+        const double fy = F32 ? (double)by : ay;
+        if (!FIRST) {
+            v.x = v.x + a.hdt * fx;
+            v.y = v.y + a.hdt * fy;
+        }
+        v.x = v.x + a.hdt * fx;
+        v.y = v.y + a.hdt * fy;
+        double2 pn;
+        pn.x = p.x + a.dt * v.x;
+        pn.y = p.y + a.dt * v.y;
+        int wx = 0, wy = 0;
+        if (pn.x >= L) { pn.x -= L; wx = 1; }
+        else if (pn.x < 0.0) { pn.x += L; wx = -1; if (pn.x >= L) { pn.x = 0.0; wx = 0; } }
+        if (pn.y >= L) { pn.y -= L; wy = 1; }
+        else if (pn.y < 0.0) { pn.y += L; wy = -1; if (pn.y >= L) { pn.y = 0.0; wy = 0; } }
+        if (wx | wy) {
+            int2 im = a.img[s];
+            im.x += wx;
+            im.y += wy;
+            a.img[s] = im;
+        }
+        if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
+        a.pout[s] = pn;
+        a.vel[s] = v;
+        if (CG) {
+            const double2 sp = a.snap[s];
+            long long cell;
+            idx = cg_index(R, *a.event_k, pn, sp, cell);
+            if (idx < MDLG_NQ && a.cell_acc) atomicAdd(&a.cell_acc[R.cacc0 + (long long)idx * R.lx * R.lx + cell], 1);
+            const double dx = min_image(pn.x - sp.x, L, halfL);
+            const double dy = min_image(pn.y - sp.y, L, halfL);
+            const double dx2 = dx * dx, dy2 = dy * dy;
+            m0 = dx2 + dy2;
+            m1 = dx2 * dx2 + dy2 * dy2;
+            m2 = dx;
+            m3 = dy;
+            a.snap[s] = pn;
+        }
+    }
+    if (CG) {
+        __syncthreads();  // hist cleared
+        const unsigned long long rest = __ballot(act && idx == 0);
+        if ((tid & 63) == 0 && rest) atomicAdd(&hist[0], (int)__popcll(rest));
+        if (act && idx != 0) atomicAdd(&hist[idx], 1);
+        m0 = wave_sum(m0);
+        m1 = wave_sum(m1);
+        m2 = wave_sum(m2);
+        m3 = wave_sum(m3);
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = m0;
+            red[tid >> 6][1] = m1;
+            red[tid >> 6][2] = m2;
+            red[tid >> 6][3] = m3;
+        }
+        __syncthreads();
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tile * MDLG_NCOUNTS + tid] = hist[tid];
+        if (tid < 4) {
+            double sum = 0.0;
+            for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
+            a.mpart[(long long)tile * MDLG_NMOMENTS + 1 + tid] = sum;
+        }
+        if (tid == 0) a.mpart[(long long)tile * MDLG_NMOMENTS] = 2.0 * (double)nact_blk;
+    }
+}
+
+// End of a coarse step: per replica and component, the fixed-order sum over
+// the replica's tiles of the histogram and moment partials is added to the
+// caller's accumulators.  Block (r, c): c < 50 counts, c >= 50 moments.
+// The last block to finish advances the coarse-step index.
+__global__ __launch_bounds__(256) void k_cg_finish(const int* __restrict__ hpart, const double* __restrict__ mpart,
+                                                   const RepDev* __restrict__ reps, unsigned long long* counts,
+                                                   double* moments, long long* event_k, unsigned int* done,
+                                                   int cell_tiles) {
+    __shared__ double red[256];
+    __shared__ long long redi[256];
+    const int r = blockIdx.x / (MDLG_NCOUNTS + MDLG_NMOMENTS);
+    const int c = blockIdx.x % (MDLG_NCOUNTS + MDLG_NMOMENTS);
+    const RepDev& R = reps[r];
+    const int tid = threadIdx.x;
+    const int b0 = cell_tiles ? R.ttile0 : R.tile0;
+    const int b1 = b0 + (cell_tiles ? R.nttile : R.ntile);
+    if (c < MDLG_NCOUNTS) {
+        long long sum = 0;
+        for (int b = b0 + tid; b < b1; b += 256) sum += hpart[(long long)b * MDLG_NCOUNTS + c];
+        redi[tid] = sum;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) redi[tid] += redi[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0 && redi[0]) counts[(long long)r * MDLG_NCOUNTS + c] += (unsigned long long)redi[0];
+    } else {
+        const int j = c - MDLG_NCOUNTS;
+        double sum = 0.0;
+        for (int b = b0 + tid; b < b1; b += 256) sum += mpart[(long long)b * MDLG_NMOMENTS + j];
+        red[tid] = sum;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) moments[(long long)r * MDLG_NMOMENTS + j] += red[0];
+    }
+    if (tid == 0) {
+        __threadfence();
+        const unsigned int prev = atomicAdd(done, 1u);
+        if (prev == gridDim.x - 1) {
+            *event_k += 1;
+            *done = 0u;
+        }
+    }
 }
 
 // Observation at the current positions: forces, full-step velocities, state
@@ -274,7 +897,7 @@ template <int BS, bool F32, bool HALF>
 __global__ __launch_bounds__(BS) void k_observe(StepArgs a) {
     __shared__ double red[BS / 64][4];
     const int tile = blockIdx.x;
-    const int r = a.tile_rep[tile];
+    const int r = __builtin_amdgcn_readfirstlane(a.tile_rep[tile]);
     const RepDev& R = a.reps[r];
     const int s = tile * BS + threadIdx.x;
     const bool act = s - R.slot0 < R.n;
@@ -349,9 +972,10 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_bin(const double2* __restrict__ pos, const RepDev* __restrict__ reps,
                                             const int* __restrict__ tile_rep, int* __restrict__ cnt,
                                             int* __restrict__ key, int* __restrict__ rank,
-                                            const int* __restrict__ cellof, int check, int* err) {
+                                            const int* __restrict__ cellof, int check, int* err,
+                                            const double2* __restrict__ pref) {
     const int tile = blockIdx.x;
-    const RepDev& R = reps[tile_rep[tile]];
+    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(tile_rep[tile])];
     const int s = tile * BS + threadIdx.x;
     int c;
     if (s - R.slot0 < R.n) {
@@ -359,17 +983,25 @@ __global__ __launch_bounds__(BS) void k_bin(const double2* __restrict__ pos, con
         const int cx = cell_coord(p.x, R.inv_w, R.nc);
         const int cy = cell_coord(p.y, R.inv_w, R.nc);
         c = R.cell0 + cy * R.nc + cx;
-        if (check) {
-            // drift check: the particle must still lie within the skin around
-            // the cell it was sorted into at the previous rebuild (checked here
-            // against half the skin, a factor-2 margin)
+        if (check && pref) {
+            // neighbour lists hold every pair within rc + skin at the list build,
+            // which covers all pairs within rc while no particle has moved more
+            // than half the skin since then
+            const double2 q = pref[s];
+            const double ex = fabs(min_image(p.x - q.x, R.L, R.halfL));
+            const double ey = fabs(min_image(p.y - q.y, R.L, R.halfL));
+            if (!(ex * ex + ey * ey <= R.skin_half * R.skin_half)) atomicOr(err, ERR_SKIN);
+        } else if (check) {
+            // the cell-stencil kernels centre the stencil on the cell a particle
+            // was sorted into, which finds every pair within rc as long as no
+            // particle has left that cell's box by more than half the skin
             const int co = cellof[s] - R.cell0;
             const int ox = co % R.nc, oy = co / R.nc;
             const double ex = fabs(min_image(p.x - (ox + 0.5) * R.w, R.L, R.halfL)) - 0.5 * R.w;
             const double ey = fabs(min_image(p.y - (oy + 0.5) * R.w, R.L, R.halfL)) - 0.5 * R.w;
             if (ex > R.skin_half || ey > R.skin_half) atomicOr(err, ERR_SKIN);
-            if (!isfinite(p.x) || !isfinite(p.y)) atomicOr(err, ERR_NONFINITE);
         }
+        if (check && (!isfinite(p.x) || !isfinite(p.y))) atomicOr(err, ERR_NONFINITE);
     } else {
         c = R.cell0 + R.nc * R.nc;  // pad slots go to the replica's sentinel cell
     }
@@ -595,12 +1227,24 @@ struct lj_md {
     int C = 0;   // total cells including one sentinel per replica
     int BS = 256;
     int ntile = 0;
+    int TT = 0;  // cell tiles of the step kernel
+    int variant = 3;  // step kernel: 1 gather, 2 LDS tile, 3 neighbour list
+    int ubatch = 8;   // gather kernel: candidate loads in flight per batch
+    int stage_max = 1 << 30;  // tile kernel staging limit (MDLG_TILE_STAGE_MAX lowers it, for tests)
     bool f32 = false;
     double dt = 0.0;
     std::vector<RepHost> reps;
     long long n_total = 0;
     RepDev* d_reps = nullptr;
     int* d_tile_rep = nullptr;
+    int* d_ttile_rep = nullptr;
+    int* d_tinfo = nullptr;
+    int* nbl = nullptr;       // neighbour lists (step kernel 3)
+    int* nbc = nullptr;
+    double2* pref = nullptr;  // positions at the list build
+    int maxnb = 0;
+    int* d_hpart = nullptr;
+    unsigned int* d_done = nullptr;
     double2* pos[2] = {nullptr, nullptr};
     double2* vel[2] = {nullptr, nullptr};
     int2* img[2] = {nullptr, nullptr};
@@ -644,6 +1288,24 @@ void clear_graphs(lj_md* md) {
     md->graphs.clear();
 }
 
+#define EXT_LAUNCH(KERNEL, BSV, GRIDV) \
+    hipExtLaunchKernelGGL(KERNEL, dim3(GRIDV), dim3(BSV), 0, st, ev0, ev1, 0, a)
+
+template <int BS, bool F32, bool FIRST, bool CG>
+void launch_step_bs(const lj_md* md, hipStream_t st, const StepArgs& a, hipEvent_t ev0, hipEvent_t ev1) {
+    if (md->variant == 2) {
+        EXT_LAUNCH((k_step_tile<BS, F32, FIRST, CG>), BS, md->TT);
+    } else if (md->variant == 3) {
+        EXT_LAUNCH((k_step_nlist<BS, F32, FIRST, CG>), BS, md->ntile);
+    } else if (md->ubatch <= 4) {
+        EXT_LAUNCH((k_step_gather<BS, F32, FIRST, CG, 4>), BS, md->ntile);
+    } else if (md->ubatch <= 8) {
+        EXT_LAUNCH((k_step_gather<BS, F32, FIRST, CG, 8>), BS, md->ntile);
+    } else {
+        EXT_LAUNCH((k_step_gather<BS, F32, FIRST, CG, 16>), BS, md->ntile);
+    }
+}
+
 StepArgs make_args(lj_md* md) {
     StepArgs a{};
     a.pin = md->pos[md->ppar];
@@ -659,6 +1321,14 @@ StepArgs make_args(lj_md* md) {
     a.snap = md->snap[md->opar];
     a.counts = md->counts;
     a.mpart = md->d_mpart;
+    a.hpart = md->d_hpart;
+    a.ttile_rep = md->d_ttile_rep;
+    a.tinfo = md->d_tinfo;
+    a.nrep = md->R;
+    a.nslots = md->S;
+    a.stage_max = md->stage_max;
+    a.nbl = md->nbl;
+    a.nbc = md->nbc;
     a.cell_acc = md->cell_acc;
     a.event_k = md->d_event_k;
     a.id = md->id[md->opar];
@@ -673,27 +1343,48 @@ StepArgs make_args(lj_md* md) {
         default: hipLaunchKernelGGL((KERNEL<512, __VA_ARGS__>), dim3(grid), dim3(512), 0, st, a); break;  \
     }
 
-hipError_t launch_step(lj_md* md, hipStream_t st, bool first, bool cg) {
+// Step kernel launch; with ev0/ev1 the events are stamped at the kernel's own
+// start and end (hipExtLaunchKernelGGL), which times the kernel alone.
+
+template <int BS, bool F32, bool FIRST, bool CG>
+void launch_step_bs(const lj_md* md, hipStream_t st, const StepArgs& a, hipEvent_t ev0, hipEvent_t ev1);
+
+template <bool F32, bool FIRST, bool CG>
+void launch_step_kernel(const lj_md* md, hipStream_t st, const StepArgs& a, hipEvent_t ev0, hipEvent_t ev1) {
+    switch (md->BS) {
+        case 64: launch_step_bs<64, F32, FIRST, CG>(md, st, a, ev0, ev1); break;
+        case 128: launch_step_bs<128, F32, FIRST, CG>(md, st, a, ev0, ev1); break;
+        case 256: launch_step_bs<256, F32, FIRST, CG>(md, st, a, ev0, ev1); break;
+        default: launch_step_bs<512, F32, FIRST, CG>(md, st, a, ev0, ev1); break;
+    }
+}
+
+hipError_t launch_step(lj_md* md, hipStream_t st, bool first, bool cg, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr) {
     StepArgs a = make_args(md);
-    const int grid = md->ntile;
     if (md->f32) {
         if (first) {
-            if (cg) { LAUNCH_BS(md->BS, k_step, true, true, true) } else { LAUNCH_BS(md->BS, k_step, true, true, false) }
+            if (cg) launch_step_kernel<true, true, true>(md, st, a, ev0, ev1);
+            else launch_step_kernel<true, true, false>(md, st, a, ev0, ev1);
         } else {
-            if (cg) { LAUNCH_BS(md->BS, k_step, true, false, true) } else { LAUNCH_BS(md->BS, k_step, true, false, false) }
+            if (cg) launch_step_kernel<true, false, true>(md, st, a, ev0, ev1);
+            else launch_step_kernel<true, false, false>(md, st, a, ev0, ev1);
         }
     } else {
         if (first) {
-            if (cg) { LAUNCH_BS(md->BS, k_step, false, true, true) } else { LAUNCH_BS(md->BS, k_step, false, true, false) }
+            if (cg) launch_step_kernel<false, true, true>(md, st, a, ev0, ev1);
+            else launch_step_kernel<false, true, false>(md, st, a, ev0, ev1);
         } else {
-            if (cg) { LAUNCH_BS(md->BS, k_step, false, false, true) } else { LAUNCH_BS(md->BS, k_step, false, false, false) }
+            if (cg) launch_step_kernel<false, false, true>(md, st, a, ev0, ev1);
+            else launch_step_kernel<false, false, false>(md, st, a, ev0, ev1);
         }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (cg) {
-        hipLaunchKernelGGL(k_reduce_rep, dim3(md->R), dim3(256), 0, st, (const double*)md->d_mpart, MDLG_NMOMENTS,
-                           (const RepDev*)md->d_reps, md->moments, 1, md->d_event_k);
+        hipLaunchKernelGGL(k_cg_finish, dim3(md->R * (MDLG_NCOUNTS + MDLG_NMOMENTS)), dim3(256), 0, st,
+                           (const int*)md->d_hpart, (const double*)md->d_mpart, (const RepDev*)md->d_reps,
+                           md->counts, md->moments, md->d_event_k, md->d_done, md->variant == 2 ? 1 : 0);
         e = hipGetLastError();
     }
     md->ppar ^= 1;
@@ -729,16 +1420,19 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     const int grid = md->ntile;
     const int check = md->have_cellof ? 1 : 0;
     switch (md->BS) {
-        case 64: hipLaunchKernelGGL(k_bin<64>, dim3(grid), dim3(64), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err); break;
-        case 128: hipLaunchKernelGGL(k_bin<128>, dim3(grid), dim3(128), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err); break;
-        case 256: hipLaunchKernelGGL(k_bin<256>, dim3(grid), dim3(256), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err); break;
-        default: hipLaunchKernelGGL(k_bin<512>, dim3(grid), dim3(512), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err); break;
+        case 64: hipLaunchKernelGGL(k_bin<64>, dim3(grid), dim3(64), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+        case 128: hipLaunchKernelGGL(k_bin<128>, dim3(grid), dim3(128), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+        case 256: hipLaunchKernelGGL(k_bin<256>, dim3(grid), dim3(256), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+        default: hipLaunchKernelGGL(k_bin<512>, dim3(grid), dim3(512), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
     }
     const int nb = (C + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C, md->bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, md->bsum, nb);
     hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C,
                        (const int*)md->bsum, md->cs);
+    if (md->variant == 2)
+        hipLaunchKernelGGL(k_tile_info, dim3((md->TT + 255) / 256), dim3(256), 0, st, (const int*)md->cs,
+                           (const RepDev*)md->d_reps, (const int*)md->d_ttile_rep, md->TT, md->d_tinfo);
     hipLaunchKernelGGL(k_scatter, dim3((S + 255) / 256), dim3(256), 0, st, (const int*)md->key,
                        (const int*)md->rank, (const int*)md->cs, md->perm, S);
     Bufs b;
@@ -754,6 +1448,10 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     b.snap_n = md->snap[o ^ 1];
     hipLaunchKernelGGL(k_sort_gather, dim3((C + 255) / 256), dim3(256), 0, st, (const int*)md->cs, md->perm, C, b,
                        md->cellof);
+    if (md->variant == 3)
+        hipLaunchKernelGGL(k_nlist_build, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
+                           (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
+                           md->maxnb, md->nbl, md->nbc, md->pref, md->d_err);
     md->ppar ^= 1;
     md->opar ^= 1;
     md->have_cellof = true;
@@ -845,6 +1543,9 @@ mdlg_status check_params(const lj_params& p, int r) {
     if (p.block_size != 0 && p.block_size != 64 && p.block_size != 128 && p.block_size != 256 && p.block_size != 512)
         return bad("block_size must be 0, 64, 128, 256 or 512");
     if (p.rebuild_every < 0) return bad("rebuild_every must be >= 0");
+    if (p.step_kernel < 0 || p.step_kernel > 3) return bad("step_kernel must be 0, 1, 2 or 3");
+    if (p.gather_batch != 0 && p.gather_batch != 4 && p.gather_batch != 8 && p.gather_batch != 16)
+        return bad("gather_batch must be 0, 4, 8 or 16");
     return MDLG_OK;
 }
 
@@ -855,6 +1556,7 @@ mdlg_status sync_check(lj_md* md, hipStream_t st) {
     if (err) {
         md->broken = true;
         if (err & ERR_NONFINITE) return fail(MDLG_ENONFINITE, "non-finite position or velocity on the device");
+        if (err & ERR_NLIST) return fail(MDLG_ECAPACITY, "a neighbour list overflowed its capacity");
         return fail(MDLG_ESKIN, "a particle drifted beyond the cell-list skin between rebuilds; lower rebuild_every or raise skin");
     }
     return MDLG_OK;
@@ -894,8 +1596,11 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     md->R = n_rep;
     md->BS = p[0].block_size ? p[0].block_size : 256;
     md->f32 = p[0].force_bits == 32;
+    md->variant = p[0].step_kernel ? p[0].step_kernel : 3;
+    md->ubatch = p[0].gather_batch ? p[0].gather_batch : 8;
+    if (const char* e = std::getenv("MDLG_TILE_STAGE_MAX")) md->stage_max = std::max(0, std::atoi(e));
     md->dt = p[0].dt;
-    long long slots = 0, cells = 0, poff = 0;
+    long long slots = 0, cells = 0, poff = 0, ttiles = 0;
     double skin_half_min = 1e300;
     for (int r = 0; r < n_rep; ++r) {
         const lj_params& q = p[r];
@@ -922,6 +1627,17 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
         h.nslots = (int)(((q.n + kPad - 1) / kPad) * kPad);
         d.tile0 = (int)(slots / md->BS);
         d.ntile = h.nslots / md->BS;
+        {
+            // cell tiles: about 0.7 * block size particles per tile on average
+            const double occ = (double)q.n / ((double)nc * nc);
+            int twt = (int)std::floor(0.7 * md->BS / std::max(occ, 1e-9));
+            twt = std::max(1, std::min(std::min(twt, 2 * md->BS), nc));
+            d.tpr = (nc + twt - 1) / twt;
+            d.tw = (nc + d.tpr - 1) / d.tpr;
+            d.ttile0 = (int)ttiles;
+            d.nttile = nc * d.tpr;
+            ttiles += d.nttile;
+        }
         d.lx = 0;
         h.poff = poff;
         cells += (long long)nc * nc + 1;
@@ -938,10 +1654,17 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     md->C = (int)cells;
     md->n_total = poff;
     md->ntile = md->S / md->BS;
+    if (ttiles >= (1LL << 31)) {
+        delete md;
+        return fail(MDLG_EINVAL, "lj_md_init: too many cell tiles");
+    }
+    md->TT = (int)ttiles;
     md->nscan = (md->C + kScanTile - 1) / kScanTile;
 
     auto A = [&](hipError_t e) { return e == hipSuccess; };
-    bool ok = A(dalloc(&md->d_reps, n_rep)) && A(dalloc(&md->d_tile_rep, md->ntile));
+    bool ok = A(dalloc(&md->d_reps, n_rep)) && A(dalloc(&md->d_tile_rep, md->ntile)) &&
+              A(dalloc(&md->d_ttile_rep, md->TT)) && A(dalloc(&md->d_hpart, (size_t)std::max(md->TT, md->ntile) * MDLG_NCOUNTS)) &&
+              A(dalloc(&md->d_done, 1)) && A(dalloc(&md->d_tinfo, (size_t)md->TT * kTileInfo));
     for (int b = 0; b < 2 && ok; ++b)
         ok = A(dalloc(&md->pos[b], md->S)) && A(dalloc(&md->vel[b], md->S)) && A(dalloc(&md->img[b], md->S)) &&
              A(dalloc(&md->id[b], md->S)) && A(dalloc(&md->snap[b], md->S));
@@ -949,17 +1672,28 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
          A(dalloc(&md->cellof, md->S)) && A(dalloc(&md->cnt, md->C)) && A(dalloc(&md->cs, (size_t)md->C + 1)) &&
          A(dalloc(&md->bsum, md->nscan)) && A(dalloc(&md->d_err, 1)) && A(dalloc(&md->d_epart, (size_t)md->ntile * 4)) &&
          A(dalloc(&md->d_eout, (size_t)n_rep * 4)) && A(dalloc(&md->d_vmax, 1)) &&
-         A(dalloc(&md->d_mpart, (size_t)md->ntile * MDLG_NMOMENTS)) && A(dalloc(&md->d_event_k, 1)) &&
+         A(dalloc(&md->d_mpart, (size_t)std::max(md->TT, md->ntile) * MDLG_NMOMENTS)) && A(dalloc(&md->d_event_k, 1)) &&
          A(hipStreamCreateWithFlags(&md->cap, hipStreamNonBlocking));
+    if (ok && md->variant == 3) {
+        // list capacity: twice the mean neighbour count of the densest replica plus 16
+        double mean_max = 0.0;
+        for (int r = 0; r < n_rep; ++r) {
+            const RepDev& d = md->reps[r].d;
+            mean_max = std::max(mean_max, 3.14159265358979 * d.w * d.w * (double)d.n / (d.L * d.L));
+        }
+        md->maxnb = std::min(512, ((int)std::ceil(2.0 * mean_max + 16.0) + 7) / 8 * 8);
+        ok = A(dalloc(&md->nbl, (size_t)md->maxnb * md->S)) && A(dalloc(&md->nbc, md->S)) && A(dalloc(&md->pref, md->S));
+    }
     if (!ok) return destroy_on_fail(md, fail(MDLG_ENOMEM, "lj_md_init: device allocation failed"));
 
     std::vector<RepDev> hd(n_rep);
-    std::vector<int> trep(md->ntile);
+    std::vector<int> trep(md->ntile), ttrep(md->TT);
     std::vector<long long> hpoff(n_rep);
     for (int r = 0; r < n_rep; ++r) {
         hd[r] = md->reps[r].d;
         hpoff[r] = md->reps[r].poff;
         for (int t = 0; t < hd[r].ntile; ++t) trep[hd[r].tile0 + t] = r;
+        for (int t = 0; t < hd[r].nttile; ++t) ttrep[hd[r].ttile0 + t] = r;
     }
     long long* d_poff = nullptr;
     if (hipMalloc((void**)&d_poff, sizeof(long long) * n_rep) != hipSuccess)
@@ -967,6 +1701,8 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     hipError_t e = hipMemcpy(md->d_reps, hd.data(), sizeof(RepDev) * n_rep, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(md->d_tile_rep, trep.data(), sizeof(int) * md->ntile, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_poff, hpoff.data(), sizeof(long long) * n_rep, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(md->d_ttile_rep, ttrep.data(), sizeof(int) * md->TT, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(md->d_done, 0, sizeof(unsigned int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_err, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_vmax, 0, sizeof(unsigned long long), st);
     // reject non-finite inputs before they reach the cell index arithmetic
@@ -1124,9 +1860,13 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nsteps, double* ms_ou
             if (e == hipSuccess) e = hipEventRecord(recs.back().b, st);
         }
         const bool ev = event_due(md, md->cg_t + 1);
-        if (e == hipSuccess) e = rec_begin(ev ? 1 : 0);
-        if (e == hipSuccess) e = launch_step(md, st, md->vel_full, ev);
-        if (e == hipSuccess) e = hipEventRecord(recs.back().b, st);
+        if (e == hipSuccess) {
+            Rec rc{nullptr, nullptr, ev ? 1 : 0};
+            e = hipEventCreate(&rc.a);
+            if (e == hipSuccess) e = hipEventCreate(&rc.b);
+            recs.push_back(rc);
+        }
+        if (e == hipSuccess) e = launch_step(md, st, md->vel_full, ev, recs.back().a, recs.back().b);
         if (e != hipSuccess) break;
         md->vel_full = false;
         md->steps_done += 1;
@@ -1202,7 +1942,7 @@ extern "C" void lj_md_destroy(lj_md* md) {
     if (!md) return;
     clear_graphs(md);
     if (md->cap) (void)hipStreamDestroy(md->cap);
-    void* ptrs[] = {md->d_reps, md->d_tile_rep, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
+    void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->d_done, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
                     md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm,
                     md->cellof, md->cnt, md->cs, md->bsum, md->d_err, md->d_epart, md->d_eout, md->d_vmax,
                     md->d_mpart, md->d_event_k};

@@ -58,6 +58,15 @@ def test_forces_match_brute_force(n, phi, kT, bits):
     (1500, 0.2, 1.0, {"block_size": 64}),
     (1777, 0.3, 5.0, {"block_size": 512, "rebuild_every": 7}),
     (700, 0.4, 20.0, {"skin": 0.2, "rebuild_every": 3}),
+    (512, 0.0784, 20.0, {"step_kernel": 2}),
+    (2000, 0.4, 20.0, {"step_kernel": 2, "block_size": 128}),
+    (1777, 0.3, 5.0, {"step_kernel": 2, "block_size": 64, "rebuild_every": 7}),
+    (3000, 0.2, 1.0, {"step_kernel": 2, "block_size": 512}),
+    (900, 0.3, 20.0, {"gather_batch": 16, "block_size": 128}),
+    (512, 0.0784, 20.0, {"step_kernel": 3}),
+    (2000, 0.4, 20.0, {"step_kernel": 3, "block_size": 128}),
+    (1777, 0.3, 5.0, {"step_kernel": 3, "block_size": 512, "rebuild_every": 7}),
+    (3000, 0.2, 1.0, {"step_kernel": 3, "skin": 0.3}),
 ])
 def test_100_steps_match_oracle(n, phi, kT, kw):
     print(f"md100 n={n} phi={phi} kT={kT} {kw}", flush=True)
@@ -103,38 +112,55 @@ def test_grid_start_potential_energy_is_zero():
     sysm.close()
 
 
-@pytest.mark.parametrize("u", [(0.0, 0.0), (0.1, -0.05)])
-def test_fused_coarse_graining_matches_oracle(u):
+@pytest.mark.parametrize("u,kernel", [((0.0, 0.0), 1), ((0.1, -0.05), 1), ((0.0, 0.0), 2), ((0.1, -0.05), 2),
+                                      ((0.0, 0.0), 3), ((0.1, -0.05), 3)])
+def test_fused_coarse_graining_matches_oracle(u, kernel):
     # the CPU-sized workload: N = 512, phi = 0.0784, kT = 20, 2000 steps,
     # 32 x 32 lattice, coarse step 50 MD steps
     import torch
     n, steps, lx, s_cg = 512, 2000, 32, 50
-    print(f"fused cg u={u}", flush=True)
+    print(f"fused cg u={u} kernel={kernel}", flush=True)
     pos0, vel0, L = mi.initial_state(n, 0.0784, 20.0, 0)
-    sysm = gpu_system(pos0, vel0, L)
+    sysm = gpu_system(pos0, vel0, L, step_kernel=kernel)
     acc = sysm.attach_cg(lx, s_cg, u=u, cell_acc=True)
-    sysm.step(steps)
+    # the fused events against the oracle's coarse-graining of the GPU's own snapshots
+    ref = omd.CGAccum(lx, cell_acc=True)
+    prev_p, prev_i = pos0, np.zeros((n, 2), np.int64)
+    for k in range(1, steps // s_cg + 1):
+        sysm.step(s_cg)
+        p, _, i = (_np(t) for t in sysm.state())
+        omd.coarse_grain(lx, L, prev_p, p, prev_i, i, k - 1, k, u=u, counts=ref.counts, cell_acc=ref.cell_acc,
+                         moments=ref.moments)
+        prev_p, prev_i = p, i.astype(np.int64)
     torch.cuda.synchronize()
     sysm.check()
+    assert acc.events == steps // s_cg
+    assert np.array_equal(_np(acc.counts)[0], ref.counts)
+    assert np.array_equal(_np(acc.cell_acc).reshape(49, lx, lx), ref.cell_acc)
+    mg = _np(acc.moments)[0]
+    assert mg[0] == ref.moments[0]
+    for j in range(1, 5):
+        assert mg[j] == pytest.approx(ref.moments[j], rel=1e-12, abs=1e-12 * mg[1] ** 0.5)
+    # and against an independent oracle run of the whole trajectory: the counts
+    # agree exactly; the moments to what the chaotic growth of rounding allows
     oacc = omd.CGAccum(lx, cell_acc=True)
     omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, steps, cg=oacc, s_cg=s_cg, u=u)
-    assert acc.events == oacc.events == steps // s_cg
     assert np.array_equal(_np(acc.counts)[0], oacc.counts)
     assert np.array_equal(_np(acc.cell_acc).reshape(49, lx, lx), oacc.cell_acc)
-    mg = _np(acc.moments)[0]
-    assert mg[0] == oacc.moments[0]
-    assert mg[1] == pytest.approx(oacc.moments[1], rel=1e-9)
-    assert mg[2] == pytest.approx(oacc.moments[2], rel=1e-9)
+    assert mg[1] == pytest.approx(oacc.moments[1], rel=1e-6)
+    assert mg[2] == pytest.approx(oacc.moments[2], rel=1e-6)
     sysm.close()
 
 
-def test_batched_replicas_equal_single_runs():
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_batched_replicas_equal_single_runs(kernel):
     import torch
 
     import paper_2101_01160_amd as m
+    print(f"batched kernel={kernel}", flush=True)
     specs = [(600, 0.0784, 20.0, 1), (1500, 0.4, 1.0, 2), (900, 0.2, 5.0, 3)]
     states = [mi.initial_state(n, phi, kT, seed) for n, phi, kT, seed in specs]
-    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10) for s in states]
+    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10, step_kernel=kernel) for s in states]
     pos = np.concatenate([s[0] for s in states])
     vel = np.concatenate([s[1] for s in states])
     batch = m.LJSystem(_cuda(pos), _cuda(vel), params=params)
@@ -145,7 +171,7 @@ def test_batched_replicas_equal_single_runs():
     off = 0
     for r, (p0, v0, L) in enumerate(states):
         n = p0.shape[0]
-        single = gpu_system(p0, v0, L, rebuild_every=10)
+        single = gpu_system(p0, v0, L, rebuild_every=10, step_kernel=kernel)
         sacc = single.attach_cg([16, 24, 20][r], 10)
         single.step(60)
         sp, sv, si = (_np(t) for t in single.state())
@@ -195,14 +221,15 @@ def test_invalid_inputs_are_rejected():
     sysm.close()
 
 
-def test_one_million_particles_sampled():
+@pytest.mark.parametrize("kw", [{}, {"step_kernel": 2}, {"step_kernel": 3}, {"step_kernel": 3, "skin": 0.665}])
+def test_one_million_particles_sampled(kw):
     # the benchmark workload: N = 2^20 at phi = 0.0784, kT = 20, 1024^2 lattice,
-    # coarse step 50, default launch configuration
+    # coarse step 50, in the benchmark's launch configurations
     import torch
     n, lx, s_cg = 1 << 20, 1024, 50
-    print("one million: init", flush=True)
+    print(f"one million: init {kw}", flush=True)
     pos0, vel0, L = mi.initial_state(n, 0.0784, 20.0, 0)
-    sysm = gpu_system(pos0, vel0, L)
+    sysm = gpu_system(pos0, vel0, L, **kw)
     acc = sysm.attach_cg(lx, s_cg)
     sysm.step(s_cg)
     pos, vel, img = (_np(t) for t in sysm.state())
@@ -225,3 +252,42 @@ def test_one_million_particles_sampled():
     assert np.max(np.abs(v1 - vo)) <= 1e-12 * np.abs(vo).max()
     sysm.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_fp32_forces_track_fp64(kernel):
+    # FP32 pair arithmetic: the trajectory stays within FP32 rounding of the FP64 oracle over 100 steps
+    n = 2000
+    print(f"fp32 kernel={kernel}", flush=True)
+    pos0, vel0, L = mi.initial_state(n, 0.4, 20.0, 4)
+    sysm = gpu_system(pos0, vel0, L, force_bits=32, step_kernel=kernel)
+    sysm.step(100)
+    pos, vel, img = (_np(t) for t in sysm.state())
+    sysm.check()
+    po, vo, io, _ = omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, 100)
+    assert np.array_equal(img, io)
+    assert np.max(np.abs((pos + L * img) - (po + L * io))) <= 1e-7
+    assert np.max(np.abs(vel - vo)) <= 1e-4 * np.abs(vo).max()
+    e = sysm.energy()[0]
+    o = omd.energy(po, vo, L)
+    assert e[0] + e[1] == pytest.approx(o[0] + o[1], rel=1e-6)
+    sysm.close()
+
+
+def test_tile_kernel_global_fallback(monkeypatch):
+    # tiles whose three rows exceed the staging limit read their neighbours from
+    # global memory; a limit of 0 sends every tile down that path
+    monkeypatch.setenv("MDLG_TILE_STAGE_MAX", "0")
+    n = 1500
+    pos0, vel0, L = mi.initial_state(n, 0.3, 20.0, 8)
+    sysm = gpu_system(pos0, vel0, L, step_kernel=2, block_size=128)
+    acc = sysm.attach_cg(12, 20)
+    sysm.step(100)
+    pos, vel, img = (_np(t) for t in sysm.state())
+    sysm.check()
+    oacc = omd.CGAccum(12)
+    po, vo, io, _ = omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, 100, cg=oacc, s_cg=20)
+    assert np.array_equal(img, io)
+    assert np.max(np.abs((pos + L * img) - (po + L * io))) <= 1e-10 * L
+    assert np.array_equal(_np(acc.counts)[0], oacc.counts)
+    sysm.close()
