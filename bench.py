@@ -51,10 +51,63 @@ def parse():
     ap.add_argument("--step-kernel", type=int, default=0)
     ap.add_argument("--gather-batch", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-baseline-steps", type=int, default=150,
+    ap.add_argument("--cpu-baseline-steps", type=int, default=500,
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
-    ap.add_argument("--timed-launches", type=int, default=100, help="eager steps timed per launch")
+    ap.add_argument("--timed-units", type=int, default=8,
+                    help="cell-list intervals replayed for kernel timing (the first two warm up)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (bandwidth and counter calibration)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_nlist_1M_phi0.0784.traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01160_amd", "csrc", "md.hip")
+
+
+def source_sha256():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(n):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    same counter reads for a plain copy of known size), or None when the
+    summary is missing, for another workload, or older than the kernel source."""
+    try:
+        kv = {}
+        for ln in open(TRAFFIC_FILE):
+            if ":" in ln and not ln.startswith("#"):
+                k, v = ln.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != source_sha256() or int(kv.get("n", -1)) != n:
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"]) * 1024.0
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]) * 1024.0
+        return fetch + write
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    import torch
+    a = torch.empty(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_mib": mib, "read_bytes": mib << 20, "write_bytes": mib << 20, "us_per_copy": ms * 1e3,
+                      "gb_per_s_read_plus_write": 2 * (mib << 20) / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def cpu_baseline(n, phi, kT, lx, s_cg, seed, steps):
@@ -74,6 +127,9 @@ def cpu_baseline(n, phi, kT, lx, s_cg, seed, steps):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not built)"}))
@@ -110,11 +166,13 @@ def main():
     value = n * md_steps / (ms * 1e-3)
     print(f"# timed {md_steps} MD steps in {ms:.2f} ms", file=sys.stderr, flush=True)
 
-    # per-launch kernel times, measured with HIP events on the launch stream
-    kms, kcnt = sysm.step_timed(args.timed_launches)
+    # kernel times as the graphs run them: HIP events on the launch stream
+    # between the graphs of a cell-list interval
+    kms, kcnt = sysm.step_timed(args.timed_units)
     sysm.check()
     t_step, t_cg, t_rebuild = (float(x) for x in kms)
     achieved = STEP_BYTES * n / (t_step * 1e-3) / 1e9
+    traffic = measured_traffic(n) if args.force_bits == 64 and args.step_kernel in (0, 3) else None
     cg_extra_ms = max(t_cg - t_step, 1e-9) if kcnt[1] else float("nan")
 
     counts = acc.counts.cpu().numpy()[0]
@@ -147,8 +205,8 @@ def main():
                    "cells_per_side": info["cells_per_side"], "rebuild_every": info["rebuild_every"],
                    "block_size": info["block_size"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step (plain MD step)", "kernel_ms": t_step,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "MD step kernel (no coarse-graining event)", "kernel_ms": t_step,
                      "bytes_per_launch": STEP_BYTES * n},
         "us_per_md_step": ms * 1e3 / md_steps,
         "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,

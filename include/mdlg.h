@@ -147,15 +147,18 @@ mdlg_status lj_md_cg_detach(lj_md* md);
  * Repeated chunks are replayed from captured HIP graphs. */
 mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream);
 
-/* Advance nsteps MD steps like lj_md_step, but launch every kernel eagerly
- * (no graph) and bracket each launch with HIP events on `stream`, to time the
- * kernels in place.  ms_out (host [3]) receives the average device time per
- * launch of: [0] the step kernel of an ordinary MD step, [1] the step kernel of
- * a coarse-graining step together with its moment reduction, [2] a cell-list
- * rebuild (all of its kernels); n_out (host [3], may be NULL) the number of
- * launches behind each average (0: none occurred, average 0).
- * Synchronises `stream`. */
-mdlg_status lj_md_step_timed(lj_md* md, int64_t nsteps, double* ms_out, int32_t* n_out, void* stream);
+/* Advance the replicas by nunits x rebuild_every MD steps like lj_md_step,
+ * timing the kernels as the captured graphs run them: each unit (one
+ * cell-list interval) is replayed as three graphs with HIP events on
+ * `stream` between them: the cell rebuild, the ordinary steps before the
+ * unit's first coarse-graining step, and the remaining steps.  ms_out (host
+ * [3]) receives the average device time of [0] one ordinary step kernel (the
+ * middle graph's time over its steps), [1] one coarse-graining step with its
+ * reduction (the last graph's time less its ordinary steps), [2] one cell
+ * rebuild; n_out (host [3], may be NULL) the number of kernels or graphs
+ * behind each average.  The first two units warm up (graph capture leaves
+ * the GPU idle) and are not averaged; nunits >= 3.  Synchronises `stream`. */
+mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_out, int32_t* n_out, void* stream);
 
 /* Copy the state out in the caller's particle order (index = position in
  * pos0).  Any output may be NULL.  pos, vel: device [n_total][2] float64

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -78,8 +79,8 @@ struct StepArgs {
     int nrep;
     int nslots;     // total slots: loads of the prologue are clamped below it
     int stage_max;  // tile kernel: largest staged particle count (<= its LDS capacity)
-    const int* __restrict__ nbl;  // neighbour lists [maxnb][S]
-    const int* __restrict__ nbc;  // neighbour counts [S]
+    const short* __restrict__ nbl;          // neighbour lists [maxnb][S]: slot offsets
+    const unsigned char* __restrict__ nbc;  // neighbour counts [S]
     int* __restrict__ cell_acc;
     const long long* __restrict__ event_k;
     // observation
@@ -674,11 +675,16 @@ __device__ __forceinline__ double recip(double x) {
 // Neighbour lists: for every slot, the slots within rc + skin (the cell width)
 // of it, found through the 3 x 3 cells right after the cell-list rebuild.
 // Layout nbl[j * S + s] (consecutive slots consecutive in memory for each j).
-// Also records the positions of the build for the next drift check.
+// An entry is the neighbour's slot relative to the particle's own slot,
+// reduced modulo the replica's particle count into [-n/2, n/2): in cell order
+// a neighbour lies within about three cell rows (also across the periodic
+// edge, after the reduction), which fits 16 bits; counts fit 8 bits.  Also
+// records the positions of the build for the next drift check.
 __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__ pos, const int* __restrict__ cs,
                                                      const RepDev* __restrict__ reps, const int* __restrict__ tile_rep,
-                                                     int BSt, int S, int maxnb, int* __restrict__ nbl,
-                                                     int* __restrict__ nbc, double2* __restrict__ pref, int* err) {
+                                                     int BSt, int S, int maxnb, short* __restrict__ nbl,
+                                                     unsigned char* __restrict__ nbc, double2* __restrict__ pref,
+                                                     int* err) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     const RepDev& R = reps[tile_rep[s / BSt]];
@@ -697,19 +703,28 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
     for (int oy = -1; oy <= 1; ++oy) {
         int rw = cy + oy;
         rw = rw < 0 ? rw + nc : (rw >= nc ? rw - nc : rw);
-        for (int ox = -1; ox <= 1; ++ox) {
-            int cl = cx + ox;
-            cl = cl < 0 ? cl + nc : (cl >= nc ? cl - nc : cl);
-            const int c = R.cell0 + rw * nc + cl;
-            for (int k = cs[c]; k < cs[c + 1]; ++k) {
-                if (k == s) continue;
-                const double2 q = pos[k];
-                const double dx = min_image_rint(p.x - q.x, R.L, invL);
-                const double dy = min_image_rint(p.y - q.y, R.L, invL);
-                if (dx * dx + dy * dy < rl2) {
-                    if (cnt < maxnb) nbl[(long long)cnt * S + s] = k;
-                    ++cnt;
-                }
+        const int base = R.cell0 + rw * nc;
+        // cells cx-1 .. cx+1 as one range, or two at the periodic edge
+        const int xl = cx > 0 ? cx - 1 : 0;
+        const int xr = cx < nc - 1 ? cx + 2 : nc;
+        const bool wrap = (cx == 0) || (cx == nc - 1);
+        const int xw = cx == 0 ? nc - 1 : 0;
+        const int a0 = cs[base + xl], a1 = cs[base + xr];
+        const int b0 = wrap ? cs[base + xw] : 0, b1 = wrap ? cs[base + xw + 1] : 0;
+        const int na = a1 - a0, tot = na + (b1 - b0);
+        for (int t = 0; t < tot; ++t) {
+            const int k = t < na ? a0 + t : b0 + (t - na);
+            if (k == s) continue;
+            const double2 q = pos[k];
+            const double dx = min_image_rint(p.x - q.x, R.L, invL);
+            const double dy = min_image_rint(p.y - q.y, R.L, invL);
+            if (dx * dx + dy * dy < rl2) {
+                int d = k - s;
+                if (2 * d >= R.n) d -= R.n;
+                else if (2 * d < -R.n) d += R.n;
+                if (d < -32768 || d > 32767) atomicOr(err, ERR_NLIST);
+                if (cnt < maxnb) nbl[(long long)cnt * S + s] = (short)d;
+                ++cnt;
             }
         }
     }
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
         atomicOr(err, ERR_NLIST);
         cnt = maxnb;
     }
-    nbc[s] = cnt;
+    nbc[s] = (unsigned char)cnt;
 }
 
 // One velocity-Verlet step, one thread per slot, pair forces over the slot's
@@ -745,30 +760,59 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
     const double2 p = a.pin[s];
     double2 v = a.vel[s];
     const int nn = act ? a.nbc[s] : 0;
+    // A wave whose particles all lie two cell widths or more inside the box has
+    // no neighbour across the periodic edge: its separations need no image.
+    const double edge = 2.0 * R.w;
+    const bool near_edge = act && (p.x < edge || p.x > L - edge || p.y < edge || p.y > L - edge);
+    const bool interior = __ballot(near_edge) == 0ull;
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
-    for (int j = 0; j < nn; ++j) {
-        const int k = a.nbl[(long long)j * S + s];
-        const double2 q = a.pin[k];
-        const double dx = min_image_rint(p.x - q.x, L, invL);
-        const double dy = min_image_rint(p.y - q.y, L, invL);
-        if (F32) {
-            const float fdx = (float)dx, fdy = (float)dy;
-            const float r2 = fdx * fdx + fdy * fdy;
-            if (r2 < rc2f) {
+    const short* __restrict__ nbl = a.nbl;
+    const int srel = s - R.slot0, nr = R.n;
+    unsigned int off = (unsigned int)s;
+    const unsigned int stride = (unsigned int)a.nslots;
+    // four neighbours per pass: four independent index loads, then four
+    // position gathers, then the arithmetic (slots past the list are masked)
+    constexpr int U = 4;
+    for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
+        int kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) kk[u] = nbl[j0 + u < nn ? off + u * stride : off];
+        double2 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int kr = srel + kk[u];
+            kr = kr < 0 ? kr + nr : (kr >= nr ? kr - nr : kr);
+            q[u] = a.pin[R.slot0 + kr];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool valid = j0 + u < nn;
+            double dx = p.x - q[u].x, dy = p.y - q[u].y;
+            if (!interior) {
+                dx = min_image_rint(dx, L, invL);
+                dy = min_image_rint(dy, L, invL);
+            }
+            if (!valid) {
+                dx = L;  // far away: no force
+                dy = L;
+            }
+            if (F32) {
+                const float fdx = (float)dx, fdy = (float)dy;
+                const float r2 = fdx * fdx + fdy * fdy;
                 const float ir2 = __builtin_amdgcn_rcpf(r2);
                 const float ir2n = ir2 * (2.0f - r2 * ir2);
                 const float ir6 = ir2n * ir2n * ir2n;
-                const float fr = eps24f * ir6 * (2.0f * ir6 - 1.0f) * ir2n;
+                float fr = eps24f * ir6 * (2.0f * ir6 - 1.0f) * ir2n;
+                fr = r2 < rc2f ? fr : 0.0f;
                 bx += fr * fdx;
                 by += fr * fdy;
-            }
-        } else {
-            const double r2 = dx * dx + dy * dy;
-            if (r2 < rc2) {
+            } else {
+                const double r2 = dx * dx + dy * dy;
                 const double ir2 = recip(r2);
                 const double ir6 = ir2 * ir2 * ir2;
-                const double fr = eps24 * ir6 * (2.0 * ir6 - 1.0) * ir2;
+                double fr = eps24 * ir6 * (2.0 * ir6 - 1.0) * ir2;
+                fr = r2 < rc2 ? fr : 0.0;
                 ax += fr * dx;
                 ay += fr * dy;
             }
@@ -1074,7 +1118,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(int* bsum, int nb) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_final(const int* __restrict__ in, long long n,
+__global__ __launch_bounds__(1024) void k_scan_final(int* __restrict__ in, long long n,
                                                      const int* __restrict__ boff, int* __restrict__ out) {
     __shared__ int lds[32];
     const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
@@ -1082,6 +1126,7 @@ __global__ __launch_bounds__(1024) void k_scan_final(const int* __restrict__ in,
     int s = 0;
     for (int j = 0; j < 4; ++j) {
         v[j] = base + j < n ? in[base + j] : 0;
+        if (base + j < n) in[base + j] = 0;  // counts start from zero at the next rebuild
         s += v[j];
     }
     int total;
@@ -1094,9 +1139,13 @@ __global__ __launch_bounds__(1024) void k_scan_final(const int* __restrict__ in,
 }
 
 __global__ void k_scatter(const int* __restrict__ key, const int* __restrict__ rank, const int* __restrict__ cs,
-                          int* __restrict__ perm, int S) {
+                          const int* __restrict__ id, int* __restrict__ perm, int* __restrict__ permid, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < S) perm[cs[key[s]] + rank[s]] = s;
+    if (s < S) {
+        const int d = cs[key[s]] + rank[s];
+        perm[d] = s;
+        permid[d] = id[s];
+    }
 }
 
 struct Bufs {
@@ -1112,32 +1161,30 @@ struct Bufs {
     double2* snap_n;
 };
 
-// One thread per cell: order the cell's particles by caller index, then move
-// their state into the new slot order.
-__global__ void k_sort_gather(const int* __restrict__ cs, int* __restrict__ perm, int C, Bufs b,
-                              int* __restrict__ cellof) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    const int lo = cs[c], hi = cs[c + 1];
-    for (int i = lo + 1; i < hi; ++i) {
-        const int x = perm[i];
-        const int kx = b.id_o[x];
-        int j = i - 1;
-        while (j >= lo && b.id_o[perm[j]] > kx) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = x;
+// One thread per slot of the scattered order: the particle's final slot is
+// its cell's first slot plus the number of particles of that cell with a
+// smaller caller index (pad slots, id -1, keep their scattered order), so the
+// order within a cell does not depend on the atomics of the binning; then its
+// state moves there.
+__global__ void k_place(const int* __restrict__ cs, const int* __restrict__ key, const int* __restrict__ perm,
+                        const int* __restrict__ permid, int S, Bufs b, int* __restrict__ cellof) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= S) return;
+    const int src = perm[d];
+    const int myid = permid[d];
+    const int c = key[src];
+    int dst = d;
+    if (myid >= 0) {
+        const int lo = cs[c], hi = cs[c + 1];
+        dst = lo;
+        for (int e = lo; e < hi; ++e) dst += permid[e] < myid ? 1 : 0;
     }
-    for (int d = lo; d < hi; ++d) {
-        const int src = perm[d];
-        b.pos_n[d] = b.pos_o[src];
-        b.vel_n[d] = b.vel_o[src];
-        b.img_n[d] = b.img_o[src];
-        b.id_n[d] = b.id_o[src];
-        b.snap_n[d] = b.snap_o[src];
-        cellof[d] = c;
-    }
+    b.pos_n[dst] = b.pos_o[src];
+    b.vel_n[dst] = b.vel_o[src];
+    b.img_n[dst] = b.img_o[src];
+    b.id_n[dst] = myid;
+    b.snap_n[dst] = b.snap_o[src];
+    cellof[dst] = c;
 }
 
 // Initial placement: slot slot0_r + j of replica r holds particle off_r + j.
@@ -1239,8 +1286,8 @@ struct lj_md {
     int* d_tile_rep = nullptr;
     int* d_ttile_rep = nullptr;
     int* d_tinfo = nullptr;
-    int* nbl = nullptr;       // neighbour lists (step kernel 3)
-    int* nbc = nullptr;
+    short* nbl = nullptr;     // neighbour lists (step kernel 3)
+    unsigned char* nbc = nullptr;
     double2* pref = nullptr;  // positions at the list build
     int maxnb = 0;
     int* d_hpart = nullptr;
@@ -1250,7 +1297,7 @@ struct lj_md {
     int2* img[2] = {nullptr, nullptr};
     int* id[2] = {nullptr, nullptr};
     double2* snap[2] = {nullptr, nullptr};
-    int *key = nullptr, *rank = nullptr, *perm = nullptr, *cellof = nullptr;
+    int *key = nullptr, *rank = nullptr, *perm = nullptr, *permid = nullptr, *cellof = nullptr;
     int *cnt = nullptr, *cs = nullptr, *bsum = nullptr;
     int nscan = 0;
     int ppar = 0, opar = 0;  // current buffer of pos / of the other per-particle arrays
@@ -1415,7 +1462,6 @@ hipError_t launch_observe(lj_md* md, hipStream_t st, double2* opos, double2* ove
 
 hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     const int S = md->S, C = md->C;
-    hipLaunchKernelGGL(k_fill_i32, dim3((C + 255) / 256), dim3(256), 0, st, md->cnt, (long long)C, 0);
     const int o = md->opar;
     const int grid = md->ntile;
     const int check = md->have_cellof ? 1 : 0;
@@ -1428,13 +1474,13 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     const int nb = (C + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C, md->bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, md->bsum, nb);
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C,
-                       (const int*)md->bsum, md->cs);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, st, md->cnt, (long long)C, (const int*)md->bsum,
+                       md->cs);
     if (md->variant == 2)
         hipLaunchKernelGGL(k_tile_info, dim3((md->TT + 255) / 256), dim3(256), 0, st, (const int*)md->cs,
                            (const RepDev*)md->d_reps, (const int*)md->d_ttile_rep, md->TT, md->d_tinfo);
     hipLaunchKernelGGL(k_scatter, dim3((S + 255) / 256), dim3(256), 0, st, (const int*)md->key,
-                       (const int*)md->rank, (const int*)md->cs, md->perm, S);
+                       (const int*)md->rank, (const int*)md->cs, (const int*)md->id[o], md->perm, md->permid, S);
     Bufs b;
     b.pos_o = md->pos[md->ppar];
     b.pos_n = md->pos[md->ppar ^ 1];
@@ -1446,8 +1492,8 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     b.id_n = md->id[o ^ 1];
     b.snap_o = md->snap[o];
     b.snap_n = md->snap[o ^ 1];
-    hipLaunchKernelGGL(k_sort_gather, dim3((C + 255) / 256), dim3(256), 0, st, (const int*)md->cs, md->perm, C, b,
-                       md->cellof);
+    hipLaunchKernelGGL(k_place, dim3((S + 255) / 256), dim3(256), 0, st, (const int*)md->cs, (const int*)md->key,
+                       (const int*)md->perm, (const int*)md->permid, S, b, md->cellof);
     if (md->variant == 3)
         hipLaunchKernelGGL(k_nlist_build, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
                            (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
@@ -1668,7 +1714,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     for (int b = 0; b < 2 && ok; ++b)
         ok = A(dalloc(&md->pos[b], md->S)) && A(dalloc(&md->vel[b], md->S)) && A(dalloc(&md->img[b], md->S)) &&
              A(dalloc(&md->id[b], md->S)) && A(dalloc(&md->snap[b], md->S));
-    ok = ok && A(dalloc(&md->key, md->S)) && A(dalloc(&md->rank, md->S)) && A(dalloc(&md->perm, md->S)) &&
+    ok = ok && A(dalloc(&md->key, md->S)) && A(dalloc(&md->rank, md->S)) && A(dalloc(&md->perm, md->S)) && A(dalloc(&md->permid, md->S)) &&
          A(dalloc(&md->cellof, md->S)) && A(dalloc(&md->cnt, md->C)) && A(dalloc(&md->cs, (size_t)md->C + 1)) &&
          A(dalloc(&md->bsum, md->nscan)) && A(dalloc(&md->d_err, 1)) && A(dalloc(&md->d_epart, (size_t)md->ntile * 4)) &&
          A(dalloc(&md->d_eout, (size_t)n_rep * 4)) && A(dalloc(&md->d_vmax, 1)) &&
@@ -1681,7 +1727,19 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             const RepDev& d = md->reps[r].d;
             mean_max = std::max(mean_max, 3.14159265358979 * d.w * d.w * (double)d.n / (d.L * d.L));
         }
-        md->maxnb = std::min(512, ((int)std::ceil(2.0 * mean_max + 16.0) + 7) / 8 * 8);
+        md->maxnb = std::min(248, ((int)std::ceil(2.0 * mean_max + 16.0) + 7) / 8 * 8);
+        for (int r = 0; r < n_rep; ++r) {
+            // list entries are 16-bit slot offsets: a neighbour lies within about
+            // three cell rows of a particle in cell order
+            const RepDev& d = md->reps[r].d;
+            if (4.0 * d.n / d.nc >= 32767.0)
+                return destroy_on_fail(md, fail(MDLG_EINVAL, "lj_md_init: replica " + std::to_string(r) +
+                                                                 " has too many particles per cell row for 16-bit "
+                                                                 "neighbour offsets; use step_kernel 1"));
+        }
+        if ((double)md->maxnb * md->S >= 1073741824.0)
+            return destroy_on_fail(md, fail(MDLG_EINVAL, "lj_md_init: neighbour lists of this size exceed 2^30 "
+                                                         "entries; use step_kernel 1"));
         ok = A(dalloc(&md->nbl, (size_t)md->maxnb * md->S)) && A(dalloc(&md->nbc, md->S)) && A(dalloc(&md->pref, md->S));
     }
     if (!ok) return destroy_on_fail(md, fail(MDLG_ENOMEM, "lj_md_init: device allocation failed"));
@@ -1704,6 +1762,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     if (e == hipSuccess) e = hipMemcpy(md->d_ttile_rep, ttrep.data(), sizeof(int) * md->TT, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_done, 0, sizeof(unsigned int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_err, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(md->cnt, 0, sizeof(int) * md->C, st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_vmax, 0, sizeof(unsigned long long), st);
     // reject non-finite inputs before they reach the cell index arithmetic
     if (e == hipSuccess) {
@@ -1833,66 +1892,168 @@ extern "C" mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream) {
     return MDLG_OK;
 }
 
-extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nsteps, double* ms_out, int32_t* n_out,
-                                        void* stream) {
+namespace {
+
+// Capture `fn` (which enqueues work on the capture stream and updates the host
+// state) into an executable graph.
+template <typename F>
+mdlg_status capture(lj_md* md, F fn, hipGraphExec_t* out) {
+    MDLG_HIP(hipStreamBeginCapture(md->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = fn(md->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(md->cap, &g);
+    if (e != hipSuccess) return fail(MDLG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    MDLG_HIP(e2);
+    hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    MDLG_HIP(e3);
+    return MDLG_OK;
+}
+
+}  // namespace
+
+extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_out, int32_t* n_out, void* stream) {
     if (!md || !ms_out) return fail(MDLG_EINVAL, "lj_md_step_timed: NULL argument");
     if (md->broken) return fail(MDLG_EINVAL, "lj_md_step_timed: handle is unusable after a device fault");
-    if (nsteps < 0 || nsteps > 100000) return fail(MDLG_EINVAL, "lj_md_step_timed: nsteps must be in [0, 1e5]");
+    if (nunits < 3 || nunits > 10000) return fail(MDLG_EINVAL, "lj_md_step_timed: nunits must be in [3, 1e4]");
     hipStream_t st = (hipStream_t)stream;
-    struct Rec {
-        hipEvent_t a, b;
-        int kind;
-    };
-    std::vector<Rec> recs;
-    auto rec_begin = [&](int kind) -> hipError_t {
-        Rec r{nullptr, nullptr, kind};
-        hipError_t e = hipEventCreate(&r.a);
-        if (e == hipSuccess) e = hipEventCreate(&r.b);
-        if (e == hipSuccess) e = hipEventRecord(r.a, st);
-        recs.push_back(r);
-        return e;
-    };
-    hipError_t e = hipSuccess;
-    for (int64_t i = 0; i < nsteps && e == hipSuccess; ++i) {
-        if (md->since_rebuild >= md->K) {
-            e = rec_begin(2);
-            if (e == hipSuccess) e = launch_rebuild(md, st);
-            if (e == hipSuccess) e = hipEventRecord(recs.back().b, st);
-        }
-        const bool ev = event_due(md, md->cg_t + 1);
-        if (e == hipSuccess) {
-            Rec rc{nullptr, nullptr, ev ? 1 : 0};
-            e = hipEventCreate(&rc.a);
-            if (e == hipSuccess) e = hipEventCreate(&rc.b);
-            recs.push_back(rc);
-        }
-        if (e == hipSuccess) e = launch_step(md, st, md->vel_full, ev, recs.back().a, recs.back().b);
-        if (e != hipSuccess) break;
-        md->vel_full = false;
-        md->steps_done += 1;
-        md->since_rebuild += 1;
-        if (md->cg_on) {
-            md->cg_t += 1;
-            if (ev) md->events += 1;
-        }
+    if (md->vel_full) {
+        hipError_t e = eager_step(md, st);
+        if (e != hipSuccess) return fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const int K = md->K;
+    // ordinary steps at the start of a unit, before its first coarse-graining step
+    int M = K;
+    if (md->cg_on) {
+        const long long to_event = md->s_cg - (md->cg_t % md->s_cg);
+        if (to_event <= K) M = (int)to_event - 1;
+    }
+    struct Key3 {
+        int ppar, opar;
+    };
+    std::vector<hipGraphExec_t> made;
+    std::map<std::pair<int, int>, std::array<hipGraphExec_t, 3>> cache;
+    std::vector<hipEvent_t> evs;
     double sum[3] = {0, 0, 0};
     int cnt[3] = {0, 0, 0};
-    for (auto& r : recs) {
-        float ms = 0.0f;
-        if (e == hipSuccess && r.a && r.b) e = hipEventElapsedTime(&ms, r.a, r.b);
-        sum[r.kind] += ms;
-        cnt[r.kind] += 1;
-        if (r.a) (void)hipEventDestroy(r.a);
-        if (r.b) (void)hipEventDestroy(r.b);
+    mdlg_status status = MDLG_OK;
+    std::vector<std::array<int, 4>> order;  // event indices per unit
+    int tail_events = 0;                     // coarse-graining steps in the last graph
+    for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
+        const auto key = std::make_pair(md->ppar, md->opar);
+        auto it = cache.find(key);
+        const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
+        std::array<hipGraphExec_t, 3> g{nullptr, nullptr, nullptr};
+        if (it == cache.end()) {
+            status = capture(md, [&](hipStream_t cs) { return launch_rebuild(md, cs); }, &g[0]);
+            if (status == MDLG_OK)
+                status = capture(md, [&](hipStream_t cs) {
+                    hipError_t e = hipSuccess;
+                    for (int j = 0; j < M && e == hipSuccess; ++j) {
+                        e = launch_step(md, cs, false, false);
+                        md->cg_t += md->cg_on ? 1 : 0;
+                    }
+                    return e;
+                }, &g[1]);
+            if (status == MDLG_OK)
+                status = capture(md, [&](hipStream_t cs) {
+                    hipError_t e = hipSuccess;
+                    for (int j = M; j < K && e == hipSuccess; ++j) {
+                        const bool ev = event_due(md, md->cg_t + 1);
+                        e = launch_step(md, cs, false, ev);
+                        if (md->cg_on) {
+                            md->cg_t += 1;
+                            if (ev) md->events += 1;
+                        }
+                    }
+                    return e;
+                }, &g[2]);
+            tail_events = (int)(md->events - ev0);
+            for (auto x : g)
+                if (x) made.push_back(x);
+            if (status != MDLG_OK) break;
+            cache[key] = g;
+            // captures only recorded work: restore the step counters
+            md->ppar = key.first;
+            md->opar = key.second;
+            md->steps_done = steps0;
+            md->cg_t = cg_t0;
+            md->events = ev0;
+        } else {
+            g = it->second;
+        }
+        std::array<int, 4> idx{};
+        for (int q = 0; q < 4; ++q) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                status = fail(MDLG_EHIP, "lj_md_step_timed: event creation failed");
+                break;
+            }
+            idx[q] = (int)evs.size();
+            evs.push_back(e);
+        }
+        if (status != MDLG_OK) break;
+        hipError_t e = hipEventRecord(evs[idx[0]], st);
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+            if (g[q]) e = hipGraphLaunch(g[q], st);
+            if (e == hipSuccess) e = hipEventRecord(evs[idx[q + 1]], st);
+        }
+        if (e != hipSuccess) {
+            status = fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
+            break;
+        }
+        order.push_back(idx);
+        // host state after the unit: the capture's effect, replayed
+        int pp = md->ppar ^ 1, op = md->opar ^ 1;  // rebuild
+        pp ^= (K & 1);                              // K steps
+        md->ppar = pp;
+        md->opar = op;
+        md->steps_done += K;
+        md->since_rebuild = K;
+        md->have_cellof = true;
+        if (md->cg_on) {
+            for (int j = 0; j < K; ++j) {
+                md->cg_t += 1;
+                if (md->cg_t % md->s_cg == 0) md->events += 1;
+            }
+        }
     }
-    if (e != hipSuccess) return fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
-    for (int k = 0; k < 3; ++k) {
-        ms_out[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
-        if (n_out) n_out[k] = cnt[k];
+    hipError_t e = hipStreamSynchronize(st);
+    if (status == MDLG_OK && e != hipSuccess) status = fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
+    if (status == MDLG_OK) {
+        // the first two units run right after the graphs were captured on the
+        // host (the GPU idled meanwhile): they warm up and are not averaged
+        const size_t skip = order.size() > 2 ? 2 : 0;
+        for (size_t ui = skip; ui < order.size(); ++ui) {
+            const auto& idx = order[ui];
+            float t[3] = {0, 0, 0};
+            for (int q = 0; q < 3; ++q) (void)hipEventElapsedTime(&t[q], evs[idx[q]], evs[idx[q + 1]]);
+            sum[2] += t[0];
+            cnt[2] += 1;
+            if (M > 0) {
+                sum[0] += t[1];
+                cnt[0] += M;
+            }
+            if (tail_events > 0) {
+                // the tail holds the coarse-graining steps; its ordinary steps are
+                // priced at the average of the middle graph
+                sum[1] += t[2];
+                cnt[1] += tail_events;
+            }
+        }
+        const double plain = cnt[0] ? sum[0] / cnt[0] : 0.0;
+        ms_out[0] = plain;
+        ms_out[1] = cnt[1] ? (sum[1] - (double)(cnt[1] / tail_events) * (K - M - tail_events) * plain) / cnt[1] : 0.0;
+        ms_out[2] = cnt[2] ? sum[2] / cnt[2] : 0.0;
+        if (n_out) {
+            n_out[0] = cnt[0];
+            n_out[1] = cnt[1];
+            n_out[2] = cnt[2];
+        }
     }
-    return MDLG_OK;
+    for (auto x : made) (void)hipGraphExecDestroy(x);
+    for (auto x : evs) (void)hipEventDestroy(x);
+    return status;
 }
 
 extern "C" mdlg_status lj_md_get_state(lj_md* md, double* pos, double* vel, int32_t* img, void* stream) {
@@ -1943,7 +2104,7 @@ extern "C" void lj_md_destroy(lj_md* md) {
     clear_graphs(md);
     if (md->cap) (void)hipStreamDestroy(md->cap);
     void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->d_done, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
-                    md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm,
+                    md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm, md->permid,
                     md->cellof, md->cnt, md->cs, md->bsum, md->d_err, md->d_epart, md->d_eout, md->d_vmax,
                     md->d_mpart, md->d_event_k};
     for (void* q : ptrs)

@@ -54,19 +54,22 @@ def test_forces_match_brute_force(n, phi, kT, bits):
 
 @pytest.mark.parametrize("n,phi,kT,kw", [
     (512, 0.0784, 20.0, {}),
-    (2000, 0.4, 20.0, {}),
-    (1500, 0.2, 1.0, {"block_size": 64}),
-    (1777, 0.3, 5.0, {"block_size": 512, "rebuild_every": 7}),
-    (700, 0.4, 20.0, {"skin": 0.2, "rebuild_every": 3}),
+    (512, 0.0784, 20.0, {"step_kernel": 1}),
+    (2000, 0.4, 20.0, {"step_kernel": 1}),
+    (1500, 0.2, 1.0, {"step_kernel": 1, "block_size": 64}),
+    (1777, 0.3, 5.0, {"step_kernel": 1, "block_size": 512, "rebuild_every": 7}),
+    (700, 0.4, 20.0, {"step_kernel": 1, "skin": 0.2, "rebuild_every": 3}),
     (512, 0.0784, 20.0, {"step_kernel": 2}),
     (2000, 0.4, 20.0, {"step_kernel": 2, "block_size": 128}),
     (1777, 0.3, 5.0, {"step_kernel": 2, "block_size": 64, "rebuild_every": 7}),
     (3000, 0.2, 1.0, {"step_kernel": 2, "block_size": 512}),
-    (900, 0.3, 20.0, {"gather_batch": 16, "block_size": 128}),
+    (900, 0.3, 20.0, {"step_kernel": 1, "gather_batch": 16, "block_size": 128}),
+    (900, 0.3, 20.0, {"step_kernel": 1, "gather_batch": 4, "block_size": 256}),
     (512, 0.0784, 20.0, {"step_kernel": 3}),
     (2000, 0.4, 20.0, {"step_kernel": 3, "block_size": 128}),
     (1777, 0.3, 5.0, {"step_kernel": 3, "block_size": 512, "rebuild_every": 7}),
     (3000, 0.2, 1.0, {"step_kernel": 3, "skin": 0.3}),
+    (700, 0.4, 20.0, {"step_kernel": 3, "skin": 0.2, "rebuild_every": 3}),
 ])
 def test_100_steps_match_oracle(n, phi, kT, kw):
     print(f"md100 n={n} phi={phi} kT={kT} {kw}", flush=True)
@@ -221,7 +224,8 @@ def test_invalid_inputs_are_rejected():
     sysm.close()
 
 
-@pytest.mark.parametrize("kw", [{}, {"step_kernel": 2}, {"step_kernel": 3}, {"step_kernel": 3, "skin": 0.665}])
+@pytest.mark.parametrize("kw", [{"step_kernel": 1}, {"step_kernel": 2}, {"step_kernel": 3},
+                                {"step_kernel": 3, "skin": 0.665}])
 def test_one_million_particles_sampled(kw):
     # the benchmark workload: N = 2^20 at phi = 0.0784, kT = 20, 1024^2 lattice,
     # coarse step 50, in the benchmark's launch configurations
