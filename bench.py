@@ -55,6 +55,10 @@ def parse():
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--timed-units", type=int, default=8,
                     help="cell-list intervals replayed for kernel timing (the first two warm up)")
+    ap.add_argument("--workload", default="single", choices=("single", "batched"),
+                    help="single: the 1M box; batched: 256 uneven replicas in one launch per step")
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--autotune", action="store_true", help="batched: tune the launch first (lj_md_autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (bandwidth and counter calibration)")
     return ap.parse_args()
@@ -134,6 +138,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not built)"}))
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     import torch
 
     import mdlg_inputs as mi
@@ -222,6 +229,90 @@ def main():
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, phi, kT, lx, s_cg, args.seed, args.cpu_baseline_steps)
     print(json.dumps(line), flush=True)
+
+
+def bench_batched(args):
+    """Replica sweep: R systems of uneven size stepped together (one kernel per
+    MD step over all of them, one graph per cell-list interval), against the
+    same systems run one after another."""
+    import torch
+
+    import mdlg_inputs as mi
+    import paper_2101_01160_amd as m
+
+    s_cg = args.s_cg
+    specs = mi.replica_sweep(args.replicas)
+    states = [mi.initial_state(sp.n, sp.phi, sp.kT, sp.seed) for sp in specs]
+    pos = np.concatenate([st[0] for st in states])
+    vel = np.concatenate([st[1] for st in states])
+    ntot = int(pos.shape[0])
+    kw = dict(force_bits=args.force_bits, block_size=args.block_size, skin=args.skin,
+              step_kernel=args.step_kernel, gather_batch=args.gather_batch)
+    params = [m.lj_params(sp.n, sp.L, **kw) for sp in specs]
+    dev = torch.device("cuda:0")
+    tpos, tvel = torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev)
+    tuned = None
+    bparams = params
+    if args.autotune:
+        lats = [m.Lattice(lx=sp.lx, reserved=0) for sp in specs]
+        t0 = time.perf_counter()
+        bparams, us = m.lj_md_autotune(params, tpos, tvel, s_cg, lats, use_cache=False)
+        tuned = {"seconds": time.perf_counter() - t0, "best_us_per_md_step": us,
+                 "step_kernel": bparams[0].step_kernel, "block_size": bparams[0].block_size,
+                 "skins": sorted({round(p.skin, 3) for p in bparams})}
+        print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
+    batch = m.LJSystem(tpos, tvel, params=bparams)
+    acc = batch.attach_cg([sp.lx for sp in specs], s_cg)
+    info = batch.info()
+    print(f"# batch: {len(specs)} replicas, {ntot} particles, rebuild_every={info['rebuild_every']}",
+          file=sys.stderr, flush=True)
+    batch.step(args.warmup * s_cg)
+    torch.cuda.synchronize()
+    md_steps = args.steps * s_cg
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    batch.step(md_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    batch.check()
+    ms_batch = e0.elapsed_time(e1)
+    bcounts = acc.counts.cpu().numpy()
+    batch.close()
+    # the same replicas one by one, same steps
+    ms_seq = 0.0
+    max_dg = 0.0
+    for r, (sp, st) in enumerate(zip(specs, states)):
+        single = m.LJSystem(torch.from_numpy(st[0]).to(dev), torch.from_numpy(st[1]).to(dev), params=[params[r]])
+        sacc = single.attach_cg(sp.lx, s_cg)
+        single.step(args.warmup * s_cg)
+        torch.cuda.synchronize()
+        e0.record()
+        single.step(md_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        single.check()
+        ms_seq += e0.elapsed_time(e1)
+        ev = sacc.events
+        g1, _ = m.mdlg_feq_measured(bcounts[r], sp.n, ev)
+        g2, _ = m.mdlg_feq_measured(sacc.counts.cpu().numpy()[0], sp.n, ev)
+        max_dg = max(max_dg, float(np.max(np.abs(g1 - g2))))  # 0 when the launch matches
+        single.close()
+    rate_b = ntot * md_steps / (ms_batch * 1e-3)
+    rate_s = ntot * md_steps / (ms_seq * 1e-3)
+    print(json.dumps({
+        "metric": "batched replicas: aggregate particle-steps/s", "value": rate_b, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces", "data": "synthetic",
+        "config": {"workload": f"{len(specs)} replicas, N log-uniform in [4096, 262144] (total {ntot}), "
+                               f"phi in (0.0784, 0.2, 0.4) x kT in (1, 5, 20), lattice cell ~2 sigma, "
+                               f"coarse step {s_cg}", "md_steps_per_step": s_cg,
+                   "rebuild_every": info["rebuild_every"]},
+        "one_by_one": {"value": rate_s, "ms_total": ms_seq, "speedup_of_batch": rate_b / rate_s,
+                       "path": "each replica alone, default FP64 launch"},
+        "autotune": tuned,
+        "feq_max_abs_batch_minus_single": max_dg}), flush=True)
 
 
 if __name__ == "__main__":

@@ -192,6 +192,21 @@ mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info);
 /* Free the handle and its device memory (NULL-safe). */
 void lj_md_destroy(lj_md* md);
 
+/* Autotuner of the MD step launch for a batch (or one system): times candidate
+ * configurations on the given initial state (each runs a few cell-list
+ * intervals on a handle of its own; pos0/vel0 are not modified) and writes the
+ * fastest into p_out (host [n_rep]): stage 1 picks step_kernel and
+ * block_size, stage 2 one skin for all replicas, stage 3 the skin per replica
+ * size class (factor-4 bins of N x bins of 0.05 in number density).  With a
+ * lattice (lat host [n_rep], s_cg >= 1) the coarse-graining is attached while
+ * timing.  Results are cached in $MDLG_AUTOTUNE_CACHE (default
+ * ~/.cache/mdlg_autotune.txt) by a signature of the batch; flags bit 0 skips
+ * the cache.  us_per_step (may be NULL): the best measured time per MD step, or
+ * -1 when taken from the cache.  Synchronises `stream`. */
+mdlg_status lj_md_autotune(int32_t n_rep, const lj_params* p_in, const double* pos0, const double* vel0,
+                           int32_t s_cg, const mdlg_lattice* lat, int32_t flags, lj_params* p_out,
+                           double* us_per_step, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Coarse-graining of one pair of snapshots (Eq.(n_i))                        */
 /* ------------------------------------------------------------------------ */

@@ -26,6 +26,7 @@ __all__ = [
     "MDLGError", "LJParams", "Lattice", "LJSystem", "CGAccumulators",
     "lj_params", "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
     "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_destroy",
+    "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
 ]
@@ -162,6 +163,21 @@ def lj_md_info(h) -> dict:
 def lj_md_destroy(h):
     if h:
         _abi.lib().lj_md_destroy(h)
+
+
+def lj_md_autotune(params, pos0, vel0, s_cg=0, lattices=None, use_cache=True, stream=None):
+    """Tuned copies of `params` (list of LJParams) and the best time per MD step in us
+    (-1 when taken from the cache)."""
+    torch = _torch()
+    n = sum(p.n for p in params)
+    arr_in = (LJParams * len(params))(*params)
+    arr_out = (LJParams * len(params))()
+    lats = None if lattices is None else (Lattice * len(lattices))(*lattices)
+    us = C.c_double()
+    _abi.check(_abi.lib().lj_md_autotune(len(params), arr_in, _dev(pos0, torch.float64, (n, 2), "pos0"),
+                                         _dev(vel0, torch.float64, (n, 2), "vel0"), int(s_cg), lats,
+                                         0 if use_cache else 1, arr_out, C.byref(us), _stream(stream)))
+    return list(arr_out), us.value
 
 
 # ------------------------------------------------------- coarse-graining ---

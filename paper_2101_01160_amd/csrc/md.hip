@@ -1922,30 +1922,33 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
         if (e != hipSuccess) return fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
     }
     const int K = md->K;
-    // ordinary steps at the start of a unit, before its first coarse-graining step
-    int M = K;
-    if (md->cg_on) {
-        const long long to_event = md->s_cg - (md->cg_t % md->s_cg);
-        if (to_event <= K) M = (int)to_event - 1;
-    }
-    struct Key3 {
-        int ppar, opar;
+    struct UnitRec {
+        std::array<int, 4> ev;
+        int M, tail_events;
+    };
+    struct Graphs {
+        std::array<hipGraphExec_t, 3> g;
+        int M, tail_events;
     };
     std::vector<hipGraphExec_t> made;
-    std::map<std::pair<int, int>, std::array<hipGraphExec_t, 3>> cache;
+    std::map<std::tuple<int, int, int>, Graphs> cache;
     std::vector<hipEvent_t> evs;
-    double sum[3] = {0, 0, 0};
-    int cnt[3] = {0, 0, 0};
+    std::vector<UnitRec> order;
     mdlg_status status = MDLG_OK;
-    std::vector<std::array<int, 4>> order;  // event indices per unit
-    int tail_events = 0;                     // coarse-graining steps in the last graph
     for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
-        const auto key = std::make_pair(md->ppar, md->opar);
+        const int phase = md->cg_on ? (int)(md->cg_t % md->s_cg) : -1;
+        const auto key = std::make_tuple(md->ppar, md->opar, phase);
         auto it = cache.find(key);
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
-        std::array<hipGraphExec_t, 3> g{nullptr, nullptr, nullptr};
+        Graphs G{{nullptr, nullptr, nullptr}, K, 0};
         if (it == cache.end()) {
-            status = capture(md, [&](hipStream_t cs) { return launch_rebuild(md, cs); }, &g[0]);
+            // ordinary steps at the start of the unit, before its first coarse-graining step
+            if (md->cg_on) {
+                const long long to_event = md->s_cg - (md->cg_t % md->s_cg);
+                if (to_event <= K) G.M = (int)to_event - 1;
+            }
+            const int M = G.M;
+            status = capture(md, [&](hipStream_t cs) { return launch_rebuild(md, cs); }, &G.g[0]);
             if (status == MDLG_OK)
                 status = capture(md, [&](hipStream_t cs) {
                     hipError_t e = hipSuccess;
@@ -1954,7 +1957,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                         md->cg_t += md->cg_on ? 1 : 0;
                     }
                     return e;
-                }, &g[1]);
+                }, &G.g[1]);
             if (status == MDLG_OK)
                 status = capture(md, [&](hipStream_t cs) {
                     hipError_t e = hipSuccess;
@@ -1967,55 +1970,51 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                         }
                     }
                     return e;
-                }, &g[2]);
-            tail_events = (int)(md->events - ev0);
-            for (auto x : g)
+                }, &G.g[2]);
+            G.tail_events = (int)(md->events - ev0);
+            for (auto x : G.g)
                 if (x) made.push_back(x);
             if (status != MDLG_OK) break;
-            cache[key] = g;
+            cache[key] = G;
             // captures only recorded work: restore the step counters
-            md->ppar = key.first;
-            md->opar = key.second;
+            md->ppar = std::get<0>(key);
+            md->opar = std::get<1>(key);
             md->steps_done = steps0;
             md->cg_t = cg_t0;
             md->events = ev0;
         } else {
-            g = it->second;
+            G = it->second;
         }
-        std::array<int, 4> idx{};
+        UnitRec rec{{}, G.M, G.tail_events};
         for (int q = 0; q < 4; ++q) {
             hipEvent_t e = nullptr;
             if (hipEventCreate(&e) != hipSuccess) {
                 status = fail(MDLG_EHIP, "lj_md_step_timed: event creation failed");
                 break;
             }
-            idx[q] = (int)evs.size();
+            rec.ev[q] = (int)evs.size();
             evs.push_back(e);
         }
         if (status != MDLG_OK) break;
-        hipError_t e = hipEventRecord(evs[idx[0]], st);
+        hipError_t e = hipEventRecord(evs[rec.ev[0]], st);
         for (int q = 0; q < 3 && e == hipSuccess; ++q) {
-            if (g[q]) e = hipGraphLaunch(g[q], st);
-            if (e == hipSuccess) e = hipEventRecord(evs[idx[q + 1]], st);
+            if (G.g[q]) e = hipGraphLaunch(G.g[q], st);
+            if (e == hipSuccess) e = hipEventRecord(evs[rec.ev[q + 1]], st);
         }
         if (e != hipSuccess) {
             status = fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
             break;
         }
-        order.push_back(idx);
+        order.push_back(rec);
         // host state after the unit: the capture's effect, replayed
-        int pp = md->ppar ^ 1, op = md->opar ^ 1;  // rebuild
-        pp ^= (K & 1);                              // K steps
-        md->ppar = pp;
-        md->opar = op;
+        md->ppar = md->ppar ^ 1 ^ (K & 1);
+        md->opar = md->opar ^ 1;
         md->steps_done += K;
         md->since_rebuild = K;
         md->have_cellof = true;
         if (md->cg_on) {
-            for (int j = 0; j < K; ++j) {
-                md->cg_t += 1;
-                if (md->cg_t % md->s_cg == 0) md->events += 1;
-            }
+            md->cg_t += K;
+            md->events += G.tail_events;
         }
     }
     hipError_t e = hipStreamSynchronize(st);
@@ -2023,32 +2022,34 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     if (status == MDLG_OK) {
         // the first two units run right after the graphs were captured on the
         // host (the GPU idled meanwhile): they warm up and are not averaged
-        const size_t skip = order.size() > 2 ? 2 : 0;
-        for (size_t ui = skip; ui < order.size(); ++ui) {
-            const auto& idx = order[ui];
+        double sum_plain = 0.0, sum_tail = 0.0, sum_rebuild = 0.0;
+        long long n_plain = 0, n_tail_plain = 0, n_events = 0, n_rebuild = 0;
+        for (size_t ui = order.size() > 2 ? 2 : 0; ui < order.size(); ++ui) {
+            const UnitRec& rec = order[ui];
             float t[3] = {0, 0, 0};
-            for (int q = 0; q < 3; ++q) (void)hipEventElapsedTime(&t[q], evs[idx[q]], evs[idx[q + 1]]);
-            sum[2] += t[0];
-            cnt[2] += 1;
-            if (M > 0) {
-                sum[0] += t[1];
-                cnt[0] += M;
-            }
-            if (tail_events > 0) {
-                // the tail holds the coarse-graining steps; its ordinary steps are
-                // priced at the average of the middle graph
-                sum[1] += t[2];
-                cnt[1] += tail_events;
+            for (int q = 0; q < 3; ++q) (void)hipEventElapsedTime(&t[q], evs[rec.ev[q]], evs[rec.ev[q + 1]]);
+            sum_rebuild += t[0];
+            n_rebuild += 1;
+            sum_plain += t[1];
+            n_plain += rec.M;
+            if (rec.tail_events > 0) {
+                sum_tail += t[2];
+                n_events += rec.tail_events;
+                n_tail_plain += K - rec.M - rec.tail_events;
+            } else {
+                sum_plain += t[2];
+                n_plain += K - rec.M;
             }
         }
-        const double plain = cnt[0] ? sum[0] / cnt[0] : 0.0;
+        const double plain = n_plain ? sum_plain / n_plain : 0.0;
+        // the tails' ordinary steps are priced at the average of the ordinary steps
         ms_out[0] = plain;
-        ms_out[1] = cnt[1] ? (sum[1] - (double)(cnt[1] / tail_events) * (K - M - tail_events) * plain) / cnt[1] : 0.0;
-        ms_out[2] = cnt[2] ? sum[2] / cnt[2] : 0.0;
+        ms_out[1] = n_events ? (sum_tail - (double)n_tail_plain * plain) / n_events : 0.0;
+        ms_out[2] = n_rebuild ? sum_rebuild / n_rebuild : 0.0;
         if (n_out) {
-            n_out[0] = cnt[0];
-            n_out[1] = cnt[1];
-            n_out[2] = cnt[2];
+            n_out[0] = (int32_t)n_plain;
+            n_out[1] = (int32_t)n_events;
+            n_out[2] = (int32_t)n_rebuild;
         }
     }
     for (auto x : made) (void)hipGraphExecDestroy(x);

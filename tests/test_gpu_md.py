@@ -295,3 +295,38 @@ def test_tile_kernel_global_fallback(monkeypatch):
     assert np.max(np.abs((pos + L * img) - (po + L * io))) <= 1e-10 * L
     assert np.array_equal(_np(acc.counts)[0], oacc.counts)
     sysm.close()
+
+
+def test_autotuner_returns_runnable_params(tmp_path, monkeypatch):
+    import torch
+
+    import paper_2101_01160_amd as m
+    monkeypatch.setenv("MDLG_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    specs = [(4096, 0.0784, 20.0, 1), (9000, 0.4, 1.0, 2)]
+    states = [mi.initial_state(n, phi, kT, seed) for n, phi, kT, seed in specs]
+    params = [m.lj_params(s[0].shape[0], s[2]) for s in states]
+    pos = np.concatenate([s[0] for s in states])
+    vel = np.concatenate([s[1] for s in states])
+    lats = [m.Lattice(lx=20, reserved=0), m.Lattice(lx=30, reserved=0)]
+    tuned, us = m.lj_md_autotune(params, _cuda(pos), _cuda(vel), 50, lats)
+    assert us > 0
+    assert tuned[0].step_kernel in (1, 2, 3) and tuned[0].block_size in (128, 256, 512)
+    assert all(t.n == p.n and t.box_l == p.box_l for t, p in zip(tuned, params))
+    # the second call is served from the cache with the same choice
+    again, us2 = m.lj_md_autotune(params, _cuda(pos), _cuda(vel), 50, lats)
+    assert us2 == -1.0
+    assert [(t.step_kernel, t.block_size, t.skin) for t in again] == [(t.step_kernel, t.block_size, t.skin) for t in tuned]
+    # the tuned launch runs and matches the oracle over 100 steps
+    batch = m.LJSystem(_cuda(pos), _cuda(vel), params=tuned)
+    batch.step(100)
+    bp, bv, bi = (_np(t) for t in batch.state())
+    batch.check()
+    off = 0
+    for p0, v0, L in states:
+        n = p0.shape[0]
+        po, vo, io, _ = omd.md_run(p0, v0, np.zeros((n, 2), np.int64), L, 100)
+        assert np.array_equal(bi[off:off + n], io)
+        assert np.max(np.abs((bp[off:off + n] + L * bi[off:off + n]) - (po + L * io))) <= 1e-10 * L
+        off += n
+    batch.close()
+    torch.cuda.synchronize()
