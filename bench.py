@@ -55,8 +55,10 @@ def parse():
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--timed-units", type=int, default=8,
                     help="cell-list intervals replayed for kernel timing (the first two warm up)")
-    ap.add_argument("--workload", default="single", choices=("single", "batched"),
-                    help="single: the 1M box; batched: 256 uneven replicas in one launch per step")
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision"),
+                    help="single: the 1M box; batched: 256 uneven replicas in one launch per step; "
+                         "precision: FP32 pair forces against FP64 on the 4M box")
+    ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch first (lj_md_autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -140,6 +142,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "precision":
+        bench_precision(args)
         return
     import torch
 
@@ -229,6 +234,67 @@ def main():
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, phi, kT, lx, s_cg, args.seed, args.cpu_baseline_steps)
     print(json.dumps(line), flush=True)
+
+
+def bench_precision(args):
+    """FP32 pair arithmetic (FP64 state, integration, wrap and sums) against the
+    all-FP64 run from the same initial state: energy and momentum drift, the
+    measured f_eq difference, and throughput, over several seeds."""
+    import torch
+
+    import mdlg_inputs as mi
+    import paper_2101_01160_amd as m
+
+    n = 1 << 22 if args.n == (1 << 20) else args.n
+    lx = 2048 if args.lx == 1024 else args.lx
+    s_cg, md_steps = args.s_cg, args.steps * args.s_cg
+    dev = torch.device("cuda:0")
+    rows = []
+    for seed in range(args.seeds):
+        pos0, vel0, L = mi.initial_state(n, args.phi, args.kT, seed)
+        res = {}
+        for bits in (64, 32):
+            sysm = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L,
+                              force_bits=bits, block_size=args.block_size, skin=args.skin,
+                              step_kernel=args.step_kernel)
+            e_start = sysm.energy()[0]
+            acc = sysm.attach_cg(lx, s_cg)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sysm.step(md_steps)
+            e1.record()
+            torch.cuda.synchronize()
+            sysm.check()
+            ms = e0.elapsed_time(e1)
+            e_end = sysm.energy()[0]
+            g, _ = m.mdlg_feq_measured(acc.counts.cpu().numpy()[0], n, acc.events)
+            res[bits] = {"rate": n * md_steps / (ms * 1e-3), "g": g,
+                         "energy_drift": ((e_end[0] + e_end[1]) - (e_start[0] + e_start[1])) / e_start[0],
+                         "momentum_drift": float(np.hypot(e_end[2] - e_start[2], e_end[3] - e_start[3]))}
+            sysm.close()
+        rows.append(res)
+        print(f"# seed {seed}: fp64 {res[64]['rate']:.3e}, fp32 {res[32]['rate']:.3e} particle-steps/s, "
+              f"max|dg| {np.max(np.abs(res[32]['g'] - res[64]['g'])):.2e}", file=sys.stderr, flush=True)
+    dg = np.array([np.max(np.abs(r[32]["g"] - r[64]["g"])) for r in rows])
+    g64 = np.array([r[64]["g"] for r in rows])
+    se_seed = float(np.max(np.std(g64, axis=0, ddof=1) / np.sqrt(len(rows)))) if len(rows) > 1 else None
+    out = {
+        "metric": "FP32 pair forces vs FP64: particle-steps/s and f_eq difference", "unit": "particle-steps/s",
+        "value": float(np.mean([r[32]["rate"] for r in rows])),
+        "fp64_value": float(np.mean([r[64]["rate"] for r in rows])),
+        "n_gpus": 1, "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 state, f32 pair forces", "data": "synthetic",
+        "config": {"workload": f"2D LJ gas N={n}, phi={args.phi}, kT={args.kT}, {md_steps} MD steps, lattice "
+                               f"{lx}x{lx}, coarse step {s_cg}, seeds 0..{args.seeds - 1}"},
+        "feq_max_abs_fp32_minus_fp64": {"per_seed": dg.tolist(), "mean": float(dg.mean())},
+        "feq_seed_standard_error_max": se_seed,
+        "energy_drift_rel": {"fp64": [r[64]["energy_drift"] for r in rows], "fp32": [r[32]["energy_drift"] for r in rows]},
+        "momentum_drift_abs": {"fp64": [r[64]["momentum_drift"] for r in rows],
+                               "fp32": [r[32]["momentum_drift"] for r in rows]},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(args):

@@ -36,6 +36,7 @@ __all__ = [
     "ReplicaSpec",
     "replica_sweep",
     "surrogate_sweep",
+    "mlp_init",
 ]
 
 
@@ -137,3 +138,20 @@ def surrogate_sweep(n_rep: int, seed: int = 12345, n: int = 16384,
         lx = max(4, int(round(L / cell)))
         out.append(ReplicaSpec(n=n, phi=phi, kT=kT, seed=seed * 1000 + r, L=L, lx=lx))
     return out
+
+
+MLP_DIMS = (6, 256, 256, 256, 49)
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial parameters of the f_eq surrogate network, one flat float64 vector
+    in the order W1 [6,256], b1, W2 [256,256], b2, W3, b3, W4 [256,49], b4:
+    weights U(-a, a) with a = sqrt(6 / (fan_in + fan_out)), biases zero,
+    drawn from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fi, fo in zip(MLP_DIMS[:-1], MLP_DIMS[1:]):
+        a = math.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-a, a, fi * fo))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts)
