@@ -267,6 +267,62 @@ mdlg_status mdlg_feq_gauss(double a2, const double* u, double* g_out);
  * remaining Poisson weight is below 1e-20.  lambda = 0 gives mdlg_feq_gauss. */
 mdlg_status mdlg_feq_wsg(double a2, double lambda, const double* u, double* g_out);
 
+/* ------------------------------------------------------------------------ */
+/* Surrogate network for f_eq (device, BF16 matrix cores)                    */
+/* ------------------------------------------------------------------------ */
+
+/* A small multilayer perceptron maps the six inputs
+ *   x = (phi, kT, dt_cg / dx, |u|, cos theta_u, sin theta_u)
+ * of an equilibrium LJ gas and its lattice (area fraction, temperature,
+ * coarse-graining time over lattice spacing in tau/sigma, the mean
+ * displacement in cells per coarse step and its direction) to the 49 values
+ * g_i = f_i^eq / rho of the D2Q49 equilibrium (Eq.(theory_feq)):
+ *   h1 = silu(x' W1 + b1), h2 = silu(h1 W2 + b2), h3 = silu(h2 W3 + b3),
+ *   g = softmax(h3 W4 + b4),  widths 6 -> 256 -> 256 -> 256 -> 49,
+ * with the fixed input scaling x' = x * (1/0.4, 1/20, 100, 1/0.2, 1, 1).
+ * It is trained on measured f_eq with the Kullback-Leibler divergence of
+ * Eq.(kullback_leibler), sum_i R_i log(R_i / g_i) averaged over the batch,
+ * as the loss, by Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ *
+ * Parameters are one flat float32 vector of MDLG_MLP_NPARAMS values:
+ * W1 [6][256] (input-major), b1 [256], W2 [256][256], b2, W3 [256][256], b3,
+ * W4 [256][49], b4 [49].  The handle keeps float32 master weights and Adam
+ * state; the matrix products read bfloat16 copies (round to nearest even) of
+ * the weights and of the layer inputs and accumulate in float32; biases,
+ * pre-activations, softmax and loss stay float32.  Arrays [B][6] and
+ * [B][49] are row-major float32. */
+#define MDLG_MLP_NPARAMS 145969
+typedef struct mdlg_mlp mdlg_mlp; /* opaque handle; owns all device state */
+
+/* Create a network with the given initial parameters (host [NPARAMS], all
+ * finite) and room for batches of up to max_batch (1 .. 2^20) samples.
+ * Synchronises the stream.  Errors: EINVAL, ENOMEM, EHIP. */
+mdlg_status mdlg_mlp_create(mdlg_mlp** out, const float* params, int32_t max_batch, void* stream);
+/* Copy the float32 master parameters to host [NPARAMS].  Synchronises. */
+mdlg_status mdlg_mlp_params(const mdlg_mlp* mlp, float* host_out, void* stream);
+/* Inference: g_out device [B][49] = network(x device [B][6]), 1 <= B <= max_batch. */
+mdlg_status mdlg_mlp_forward(mdlg_mlp* mlp, const float* x, int32_t B, float* g_out, void* stream);
+/* Loss and its gradient at the current parameters, without an update:
+ * target device [B][49] (rows summing to one), loss device [1] and grad
+ * device [NPARAMS] (either may be NULL). */
+mdlg_status mdlg_mlp_gradient(mdlg_mlp* mlp, const float* x, const float* target, int32_t B,
+                              float* loss, float* grad, void* stream);
+/* One training step: forward, loss, backward and an Adam update with
+ * learning rate lr > 0.  loss device [1] (may be NULL) receives the loss
+ * before the update. */
+mdlg_status mdlg_mlp_train_step(mdlg_mlp* mlp, const float* x, const float* target, int32_t B,
+                                float lr, float* loss, void* stream);
+/* Surrogate f_eq with a closed-form guard: evaluates the network at host
+ * x[6], compares it with the Poisson-WSG equilibrium (Eq.(f_eq_wsg)) of the
+ * given a2 and lambda at the drift u = |u| (cos, sin), and returns the
+ * network's values when max_i |g_net - g_wsg| <= tol, else the WSG values
+ * with *used_fallback = 1.  g_out host [49]; err host (may be NULL) gets the
+ * max difference.  Synchronises.  Errors: EINVAL, EHIP. */
+mdlg_status mdlg_feq_surrogate(mdlg_mlp* mlp, const double* x, double a2, double lambda, double tol,
+                               double* g_out, int32_t* used_fallback, double* err, void* stream);
+/* Release the handle and its device memory (NULL is ignored). */
+void mdlg_mlp_destroy(mdlg_mlp* mlp);
+
 #ifdef __cplusplus
 }
 #endif

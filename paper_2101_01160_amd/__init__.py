@@ -29,7 +29,11 @@ __all__ = [
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
+    "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
+    "mdlg_feq_surrogate", "mdlg_mlp_destroy", "SurrogateMLP", "MLP_NPARAMS",
 ]
+
+MLP_NPARAMS = _abi.MLP_NPARAMS
 
 
 def _torch():
@@ -235,6 +239,103 @@ def mdlg_feq_wsg(a2, lam, u=(0.0, 0.0)):
     _abi.check(_abi.lib().mdlg_feq_wsg(float(a2), float(lam), uu.ctypes.data_as(C.c_void_p),
                                        g.ctypes.data_as(C.c_void_p)))
     return g
+
+
+# ------------------------------------------------------ surrogate network ---
+
+def mdlg_mlp_create(params, max_batch, stream=None) -> C.c_void_p:
+    p = _host(params, np.float32, MLP_NPARAMS)
+    h = C.c_void_p()
+    _abi.check(_abi.lib().mdlg_mlp_create(C.byref(h), p.ctypes.data_as(C.c_void_p), int(max_batch), _stream(stream)))
+    return h
+
+
+def mdlg_mlp_params(h, stream=None) -> np.ndarray:
+    out = np.zeros(MLP_NPARAMS, dtype=np.float32)
+    _abi.check(_abi.lib().mdlg_mlp_params(h, out.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return out
+
+
+def mdlg_mlp_forward(h, x, g_out=None, stream=None):
+    torch = _torch()
+    B = int(x.shape[0])
+    if g_out is None:
+        g_out = torch.empty((B, 49), dtype=torch.float32, device=x.device)
+    _abi.check(_abi.lib().mdlg_mlp_forward(h, _dev(x, torch.float32, (B, 6), "x"), B,
+                                           _dev(g_out, torch.float32, (B, 49), "g_out"), _stream(stream)))
+    return g_out
+
+
+def mdlg_mlp_gradient(h, x, target, stream=None):
+    """Returns (loss tensor [1], grad tensor [NPARAMS]) on the device."""
+    torch = _torch()
+    B = int(x.shape[0])
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+    _abi.check(_abi.lib().mdlg_mlp_gradient(h, _dev(x, torch.float32, (B, 6), "x"),
+                                            _dev(target, torch.float32, (B, 49), "target"), B,
+                                            _dev(loss, torch.float32), _dev(grad, torch.float32), _stream(stream)))
+    return loss, grad
+
+
+def mdlg_mlp_train_step(h, x, target, lr, loss=None, stream=None):
+    torch = _torch()
+    B = int(x.shape[0])
+    _abi.check(_abi.lib().mdlg_mlp_train_step(h, _dev(x, torch.float32, (B, 6), "x"),
+                                              _dev(target, torch.float32, (B, 49), "target"), B, float(lr),
+                                              _dev(loss, torch.float32, (1,), "loss"), _stream(stream)))
+    return loss
+
+
+def mdlg_feq_surrogate(h, x, a2, lam, tol=1e-3, stream=None):
+    """Returns (g [49] float64, used_fallback bool, max |g_net - g_wsg|)."""
+    xx = _host(x, np.float64, 6)
+    g = np.zeros(49)
+    fb = C.c_int32(0)
+    err = C.c_double(0.0)
+    _abi.check(_abi.lib().mdlg_feq_surrogate(h, xx.ctypes.data_as(C.c_void_p), float(a2), float(lam), float(tol),
+                                             g.ctypes.data_as(C.c_void_p), C.byref(fb), C.byref(err),
+                                             _stream(stream)))
+    return g, bool(fb.value), float(err.value)
+
+
+def mdlg_mlp_destroy(h):
+    _abi.lib().mdlg_mlp_destroy(h)
+
+
+class SurrogateMLP:
+    """Owns one mdlg_mlp handle."""
+
+    def __init__(self, params, max_batch, stream=None):
+        self.stream = stream
+        self.max_batch = int(max_batch)
+        self.handle = mdlg_mlp_create(params, max_batch, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mdlg_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        return mdlg_mlp_params(self.handle, self.stream)
+
+    def forward(self, x):
+        return mdlg_mlp_forward(self.handle, x, stream=self.stream)
+
+    def gradient(self, x, target):
+        return mdlg_mlp_gradient(self.handle, x, target, self.stream)
+
+    def train_step(self, x, target, lr, loss=None):
+        return mdlg_mlp_train_step(self.handle, x, target, lr, loss, self.stream)
+
+    def feq(self, x, a2, lam, tol=1e-3):
+        return mdlg_feq_surrogate(self.handle, x, a2, lam, tol, self.stream)
 
 
 # ------------------------------------------------------ convenience class ---

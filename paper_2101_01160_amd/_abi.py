@@ -23,7 +23,11 @@ EXPORTS = [
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg",
+    "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
+    "mdlg_feq_surrogate", "mdlg_mlp_destroy",
 ]
+
+MLP_NPARAMS = 145969
 
 
 class LJParams(C.Structure):
@@ -69,6 +73,20 @@ class MDLGError(RuntimeError):
         self.status = status
 
 
+def _init_device_runtime():
+    """PyTorch carries its own copy of the HIP runtime.  Its device context is
+    brought up before the library (linked to the system HIP runtime) loads:
+    loaded the other way round, the library's first HIP call can report that
+    no device exists."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+        torch.cuda.current_stream().synchronize()
+
+
 def lib() -> C.CDLL:
     global _lib
     if _lib is not None:
@@ -76,6 +94,7 @@ def lib() -> C.CDLL:
     if not os.path.exists(LIBPATH):
         raise ImportError(f"libmdlg.so is not built ({LIBPATH}); run __graft_entry__.build() or "
                           "python paper_2101_01160_amd/build.py")
+    _init_device_runtime()
     L = C.CDLL(LIBPATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = C.POINTER
@@ -102,6 +121,13 @@ def lib() -> C.CDLL:
         "mdlg_lambda_from_moments": (i32, [dbl, dbl, i32, P(dbl), P(dbl)]),
         "mdlg_feq_gauss": (i32, [dbl, vp, vp]),
         "mdlg_feq_wsg": (i32, [dbl, dbl, vp, vp]),
+        "mdlg_mlp_create": (i32, [P(vp), vp, i32, vp]),
+        "mdlg_mlp_params": (i32, [vp, vp, vp]),
+        "mdlg_mlp_forward": (i32, [vp, vp, i32, vp, vp]),
+        "mdlg_mlp_gradient": (i32, [vp, vp, vp, i32, vp, vp, vp]),
+        "mdlg_mlp_train_step": (i32, [vp, vp, vp, i32, C.c_float, vp, vp]),
+        "mdlg_feq_surrogate": (i32, [vp, vp, dbl, dbl, dbl, vp, P(i32), P(dbl), vp]),
+        "mdlg_mlp_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
