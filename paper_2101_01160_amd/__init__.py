@@ -27,7 +27,7 @@ __all__ = [
     "lj_params", "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
     "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_destroy",
     "lj_md_autotune",
-    "mdlg_coarse_grain", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
+    "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy", "SurrogateMLP", "MLP_NPARAMS",
@@ -199,6 +199,28 @@ def mdlg_coarse_grain(lx, box_l, pos_prev, pos_cur, counts, moments=None, img_pr
         _dev(counts, torch.int64, (50,), "counts"), _dev(moments, torch.float64, (5,), "moments"),
         _dev(n_event, torch.int32, (49, lx, lx), "n_event"), _dev(cell_acc, torch.int32, (49, lx, lx), "cell_acc"),
         _stream(stream)))
+
+
+def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, moments=None, stream=None):
+    """pos: torch float64 [P, n_tot, 2], img: torch int32 [P, n_tot, 2] on the GPU;
+    counts: torch int64 [n_rep, n_lag, n_u, 50]; moments: torch float64 [n_rep, n_lag, 5]."""
+    torch = _torch()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_rep = off.size - 1
+    box = _host(box_l, np.float64, n_rep)
+    lxs = _host(lx, np.int32, n_rep)
+    lg = np.ascontiguousarray(lags, dtype=np.int32).ravel()
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 2)
+    P, n_tot = int(pos.shape[0]), int(pos.shape[1])
+    if n_tot != int(off[-1]):
+        raise ValueError("pos holds a different particle count than offsets")
+    _abi.check(_abi.lib().mdlg_coarse_grain_series(
+        int(n_rep), off.ctypes.data_as(C.c_void_p), box.ctypes.data_as(C.c_void_p),
+        lxs.ctypes.data_as(C.c_void_p), P, _dev(pos, torch.float64, (P, n_tot, 2), "pos"),
+        _dev(img, torch.int32, (P, n_tot, 2), "img"), int(lg.size), lg.ctypes.data_as(C.c_void_p),
+        int(uu.shape[0]), uu.ctypes.data_as(C.c_void_p),
+        _dev(counts, torch.int64, (n_rep, lg.size, uu.shape[0], 50), "counts"),
+        _dev(moments, torch.float64, (n_rep, lg.size, 5), "moments"), _stream(stream)))
 
 
 # ------------------------------------------------------------ equilibria ---
