@@ -55,11 +55,14 @@ def parse():
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--timed-units", type=int, default=8,
                     help="cell-list intervals replayed for kernel timing (the first two warm up)")
-    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision", "surrogate"),
                     help="single: the 1M box; batched: 256 uneven replicas in one launch per step; "
                          "precision: FP32 pair forces against FP64 on the 4M box")
     ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
     ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
+    ap.add_argument("--train-batch", type=int, default=4096, help="surrogate: minibatch")
+    ap.add_argument("--groups", type=int, default=4, help="surrogate: replica groups (80 replicas each)")
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch first (lj_md_autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (bandwidth and counter calibration)")
@@ -145,6 +148,9 @@ def main():
         return
     if args.workload == "precision":
         bench_precision(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
     import torch
 
@@ -379,6 +385,92 @@ def bench_batched(args):
                        "path": "each replica alone, default FP64 launch"},
         "autotune": tuned,
         "feq_max_abs_batch_minus_single": max_dg}), flush=True)
+
+
+MLP_FLOP_PER_SAMPLE = 2.0 * (6 * 256 + 256 * 256 * 2 + 256 * 49)  # forward products
+
+
+def bench_surrogate(args):
+    """Surrogate f_eq: GPU-generated MDLG data (batched MD + trajectory
+    coarse-graining), training on the GPU, held-out errors against measured
+    f_eq and the WSG closed form, inference throughput on the matrix cores,
+    and the cost of the same f_eq values by molecular dynamics."""
+    import torch
+
+    import paper_2101_01160_amd as m
+    from paper_2101_01160_amd import surrogate as S
+
+    log = lambda s: print("# " + s, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    data = S.generate(n_groups=args.groups, reps_per_group=80, n=65536, n_snap=201, equil=2000, log=log)
+    t_gen = time.perf_counter() - t0
+    tr, va, te = S.split_by_replica(data)
+    net, hist = S.train(data, tr, steps=args.train_steps, batch=args.train_batch, val_idx=va,
+                        val_every=max(1, args.train_steps // 8), log=log)
+    res = S.evaluate(net, data, te, with_guard=True)
+    log(f"held-out: {res}")
+    # the guard through the C entry point on a sample of held-out points
+    sample = te[:: max(1, len(te) // 64)]
+    agree = 0
+    for i in sample:
+        g, fb, err = net.feq(data.X[i], data.a2[i], data.lam[i], tol=1e-3)
+        agree += int(fb == (err > 1e-3))
+    # inference throughput: one launch sequence for a large batch, HIP events
+    B = 65536
+    big = m.SurrogateMLP(net.params(), B)
+    xb = torch.from_numpy(np.resize(data.X[te], (B, 6)).astype(np.float32)).cuda()
+    out = torch.empty((B, 49), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        m.mdlg_mlp_forward(big.handle, xb, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps // 5)
+    e0.record()
+    for _ in range(reps):
+        m.mdlg_mlp_forward(big.handle, xb, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_inf = e0.elapsed_time(e1) / reps
+    tflops = MLP_FLOP_PER_SAMPLE * B / (ms_inf * 1e-3) / 1e12
+    # training step time (GPU work plus launch overhead), fixed batch
+    x4 = torch.from_numpy(data.X[tr[:args.train_batch]].astype(np.float32)).cuda()
+    r4 = torch.from_numpy((data.G[tr[:args.train_batch]] /
+                           data.G[tr[:args.train_batch]].sum(axis=1, keepdims=True)).astype(np.float32)).cuda()
+    lbuf = torch.zeros(1, dtype=torch.float32, device="cuda")
+    probe = m.SurrogateMLP(net.params(), args.train_batch)
+    for _ in range(3):
+        probe.train_step(x4, r4, 1e-6, lbuf)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(50):
+        probe.train_step(x4, r4, 1e-6, lbuf)
+    e1.record()
+    torch.cuda.synchronize()
+    us_train = e0.elapsed_time(e1) / 50 * 1e3
+    # MD route to the same f_eq values: particle-steps per sample of the generator
+    steps_per_sample = data.timing["particle_steps"] / len(data)
+    sec_md_per_sample = (data.timing["md_s"] + data.timing["cg_s"]) / len(data)
+    sec_nn_per_sample = ms_inf * 1e-3 / B
+    rate = B / (ms_inf * 1e-3)
+    print(json.dumps({
+        "metric": "surrogate f_eq evaluations/s (6 -> 256x3 -> 49, BF16 MFMA)", "value": rate,
+        "unit": "f_eq/s", "n_gpus": 1, "steps": reps, "warmup": 3, "ms_per_step": ms_inf,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
+        "data": "synthetic (GPU MD of random-init LJ gases)",
+        "config": {"workload": f"{len(data)} samples: {args.groups * 80} replicas x 65536 particles, "
+                               f"phi~U(0.05,0.4), kT~U(1,20), 10 coarse times 10..200 MD steps, 16 drifts |u|<=0.2; "
+                               f"inference batch {B}", "train_steps": args.train_steps,
+                   "train_batch": args.train_batch},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tflops / 2500.0, "traffic": None},
+        "heldout": res, "guard_agreement": agree / len(sample),
+        "timing": {"generate_s": t_gen, "md_s": data.timing["md_s"], "coarse_grain_s": data.timing["cg_s"],
+                   "train_s": hist["train_s"], "train_step_us": us_train, "inference_us_per_batch": ms_inf * 1e3},
+        "gain": {"md_particle_steps_per_feq": steps_per_sample, "md_seconds_per_feq": sec_md_per_sample,
+                 "surrogate_seconds_per_feq": sec_nn_per_sample,
+                 "speedup": sec_md_per_sample / sec_nn_per_sample,
+                 "equivalent_particle_steps_per_s": steps_per_sample * rate}}), flush=True)
 
 
 if __name__ == "__main__":

@@ -51,6 +51,9 @@ def _load():
     lib.orc_coarse_grain.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, _i32p, C.c_int64,
                                      _dp, C.c_void_p, C.c_int64, _dp, C.c_void_p, C.c_int64,
                                      _i64p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.orc_coarse_grain_shift.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, _i32p, C.c_int64, _dp, C.c_void_p, _dp, C.c_void_p,
+                                           _i64p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.orc_coarse_grain_literal.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, _i32p,
                                              C.c_int64, _dp, C.c_int64, _dp, C.c_int64, _i64p,
                                              C.c_void_p]
@@ -144,6 +147,24 @@ def coarse_grain(lx, L, pos_prev, pos_cur, img_prev=None, img_cur=None, k_prev=0
     lib.orc_coarse_grain(lx, L, u[0], u[1], vtab, n, pos_prev, _ptr(ip), k_prev, pos_cur, _ptr(ic), k_cur,
                          counts, _ptr(n_event), _ptr(cell_acc), _ptr(moments))
     return counts, n_event, moments
+
+
+def coarse_grain_shift(lx, L, pos_prev, pos_cur, img_prev, img_cur, shift_prev, shift_cur, counts=None,
+                       moments=None):
+    """One binned event on a lattice translated by shift_prev / shift_cur (lengths, [2] each).
+    Returns (counts, moments)."""
+    lib = _load()
+    pos_prev, pos_cur = _f64(pos_prev), _f64(pos_cur)
+    n = pos_prev.shape[0]
+    vtab = lattice.d2q49()
+    counts = np.zeros(50, dtype=np.int64) if counts is None else counts
+    moments = np.zeros(5) if moments is None else moments
+    ip = None if img_prev is None else _i64(img_prev)
+    ic = None if img_cur is None else _i64(img_cur)
+    lib.orc_coarse_grain_shift(lx, L, float(shift_prev[0]), float(shift_prev[1]), float(shift_cur[0]),
+                               float(shift_cur[1]), vtab, n, pos_prev, _ptr(ip), pos_cur, _ptr(ic), counts, None,
+                               None, _ptr(moments))
+    return counts, moments
 
 
 def coarse_grain_literal(lx, L, pos_prev, pos_cur, k_prev=0, k_cur=1, u=(0.0, 0.0)):

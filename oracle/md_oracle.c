@@ -214,17 +214,19 @@ static int64_t pmod(int64_t a, int64_t m) {
  * mod lx; the unwrapped cell adds lx times the periodic image count. */
 static int64_t lattice_q(double x, double s, double inv) { return (int64_t)floor((x + s) * inv); }
 
-/* One coarse-graining event between two snapshots (binned form).
+/* One coarse-graining event between two snapshots (binned form), on a lattice
+ * translated by (sxp, syp) at the earlier snapshot and by (sxc, syc) at the
+ * later one (lengths).  A lattice moving u cells per coarse step has shifts
+ * u dx k; a common translation of both is another origin of the same lattice,
+ * which leaves the statistics of a homogeneous gas unchanged.
  * pos_*: [n][2] wrapped positions; img_*: [n][2] image counts (NULL = zero).
  * n_event: dense n_i(x, t) [49][lx][lx], overwritten (NULL to skip). */
-void orc_coarse_grain(int32_t lx, double L, double ux, double uy, const int32_t* vtab, int64_t n,
-                      const double* pos_prev, const int64_t* img_prev, int64_t k_prev,
-                      const double* pos_cur, const int64_t* img_cur, int64_t k_cur,
-                      int64_t* counts, int32_t* n_event, int32_t* cell_acc, double* moments) {
-    double dxl = L / (double)lx;
+void orc_coarse_grain_shift(int32_t lx, double L, double sxp, double syp, double sxc, double syc,
+                            const int32_t* vtab, int64_t n,
+                            const double* pos_prev, const int64_t* img_prev,
+                            const double* pos_cur, const int64_t* img_cur,
+                            int64_t* counts, int32_t* n_event, int32_t* cell_acc, double* moments) {
     double inv = (double)lx / L;
-    double sxp = (ux * dxl) * (double)k_prev, syp = (uy * dxl) * (double)k_prev;
-    double sxc = (ux * dxl) * (double)k_cur, syc = (uy * dxl) * (double)k_cur;
     int64_t lx2 = (int64_t)lx * lx;
     if (n_event) memset(n_event, 0, sizeof(int32_t) * NQ * lx2);
     nsum m2 = {0, 0}, m4 = {0, 0}, mx = {0, 0}, my = {0, 0};
@@ -265,6 +267,18 @@ void orc_coarse_grain(int32_t lx, double L, double ux, double uy, const int32_t*
         moments[3] += nsum_get(&mx);
         moments[4] += nsum_get(&my);
     }
+}
+
+/* The event at coarse steps k_prev, k_cur of a lattice moving u cells per step. */
+void orc_coarse_grain(int32_t lx, double L, double ux, double uy, const int32_t* vtab, int64_t n,
+                      const double* pos_prev, const int64_t* img_prev, int64_t k_prev,
+                      const double* pos_cur, const int64_t* img_cur, int64_t k_cur,
+                      int64_t* counts, int32_t* n_event, int32_t* cell_acc, double* moments) {
+    double dxl = L / (double)lx;
+    double sxp = (ux * dxl) * (double)k_prev, syp = (uy * dxl) * (double)k_prev;
+    double sxc = (ux * dxl) * (double)k_cur, syc = (uy * dxl) * (double)k_cur;
+    orc_coarse_grain_shift(lx, L, sxp, syp, sxc, syc, vtab, n, pos_prev, img_prev, pos_cur, img_cur,
+                           counts, n_event, cell_acc, moments);
 }
 
 /* The same event evaluated literally from Eq.(n_i): for every lattice cell x

@@ -201,9 +201,11 @@ def mdlg_coarse_grain(lx, box_l, pos_prev, pos_cur, counts, moments=None, img_pr
         _stream(stream)))
 
 
-def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, moments=None, stream=None):
+def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, moments=None, lattice_offset=None,
+                             stream=None):
     """pos: torch float64 [P, n_tot, 2], img: torch int32 [P, n_tot, 2] on the GPU;
-    counts: torch int64 [n_rep, n_lag, n_u, 50]; moments: torch float64 [n_rep, n_lag, 5]."""
+    counts: torch int64 [n_rep, n_lag, n_u, 50]; moments: torch float64 [n_rep, n_lag, 5];
+    lattice_offset: host [P, 2] lattice origin (cells) of the pairs starting at each snapshot."""
     torch = _torch()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     n_rep = off.size - 1
@@ -212,13 +214,14 @@ def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, mome
     lg = np.ascontiguousarray(lags, dtype=np.int32).ravel()
     uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 2)
     P, n_tot = int(pos.shape[0]), int(pos.shape[1])
+    lo = None if lattice_offset is None else _host(lattice_offset, np.float64, 2 * P)
     if n_tot != int(off[-1]):
         raise ValueError("pos holds a different particle count than offsets")
     _abi.check(_abi.lib().mdlg_coarse_grain_series(
         int(n_rep), off.ctypes.data_as(C.c_void_p), box.ctypes.data_as(C.c_void_p),
         lxs.ctypes.data_as(C.c_void_p), P, _dev(pos, torch.float64, (P, n_tot, 2), "pos"),
         _dev(img, torch.int32, (P, n_tot, 2), "img"), int(lg.size), lg.ctypes.data_as(C.c_void_p),
-        int(uu.shape[0]), uu.ctypes.data_as(C.c_void_p),
+        int(uu.shape[0]), uu.ctypes.data_as(C.c_void_p), None if lo is None else lo.ctypes.data_as(C.c_void_p),
         _dev(counts, torch.int64, (n_rep, lg.size, uu.shape[0], 50), "counts"),
         _dev(moments, torch.float64, (n_rep, lg.size, 5), "moments"), _stream(stream)))
 

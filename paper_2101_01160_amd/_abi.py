@@ -116,7 +116,7 @@ def lib() -> C.CDLL:
         "lj_md_destroy": (None, [vp]),
         "lj_md_autotune": (i32, [i32, P(LJParams), vp, vp, i32, P(Lattice), i32, P(LJParams), P(dbl), vp]),
         "mdlg_coarse_grain": (i32, [P(Lattice), dbl, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]),
-        "mdlg_coarse_grain_series": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp]),
+        "mdlg_coarse_grain_series": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]),
         "mdlg_feq_measured": (i32, [vp, i64, i64, i32, vp, P(dbl)]),
         "mdlg_moments": (i32, [vp, dbl, P(dbl), P(dbl), P(dbl)]),
         "mdlg_lambda_from_moments": (i32, [dbl, dbl, i32, P(dbl), P(dbl)]),

@@ -3,11 +3,12 @@
 //
 // Snapshots p = 0 .. P-1 of a batch of replicas are stacked as
 // pos[P][n_tot][2], img[P][n_tot][2].  A job (l, u) takes every pair
-// (p - l, p): lattice cell of the earlier snapshot with no frame shift, of the
-// later one shifted by u dx (one coarse step of a lattice moving u cells per
-// coarse step), so each pair is one event of mdlg_coarse_grain with
-// k_prev = 0, k_cur = 1.  On a spatially homogeneous gas the frame origin does
-// not bias the counts; resetting it per pair lets overlapping pairs serve.
+// (p - l, p): the lattice of the pair is translated by o dx at the earlier
+// snapshot and by (o + u) dx at the later one (one coarse step of a lattice
+// moving u cells per coarse step), with o = offset[p - l] the origin chosen for
+// pairs starting at snapshot p - l.  A homogeneous gas has the same statistics
+// under every translation of the lattice; origins that vary between pairs
+// decorrelate the cell-crossing events of overlapping pairs.
 //
 // One thread per particle walks the snapshots once.  A ring in LDS keeps its
 // last lmax snapshots, so every snapshot is read from HBM once for all jobs;
@@ -48,7 +49,9 @@ struct SeriesArgs {
     const int* __restrict__ lx;        // [n_rep]
     const double* __restrict__ inv;    // [n_rep] lx / L
     const double* __restrict__ box;    // [n_rep] L
-    const double* __restrict__ shift;  // [n_rep][n_u][2] u dx
+    const double* __restrict__ dxl;    // [n_rep] L / lx
+    const double* __restrict__ u;      // [n_u][2] cells per coarse step
+    const double* __restrict__ off;    // [n_snap][2] lattice origin per pair start, cells
     const int* __restrict__ lags;      // [n_lag]
     unsigned long long* __restrict__ counts;  // [n_rep][n_lag][n_u][50]
     double* __restrict__ mpart;               // [n_blocks][n_lag][4]
@@ -59,6 +62,16 @@ __device__ __forceinline__ double delta_box(double xc, double xp, int di, double
     double d = xc - xp;
     double w = L * (double)di;
     return d + w;
+}
+
+// lattice shift arithmetic, each operation rounded once as written
+__device__ __forceinline__ double scaled(double o, double dxl) {
+#pragma clang fp contract(off)
+    return o * dxl;
+}
+__device__ __forceinline__ double sum(double a, double b) {
+#pragma clang fp contract(off)
+    return a + b;
 }
 
 __global__ __launch_bounds__(kSeriesBS) void k_cg_series(SeriesArgs a) {
@@ -80,8 +93,7 @@ __global__ __launch_bounds__(kSeriesBS) void k_cg_series(SeriesArgs a) {
     const long long j = blk.start + (act ? tid : 0);
     const int r = blk.rep;
     const long long lx = a.lx[r];
-    const double inv = a.inv[r], L = a.box[r];
-    const double* sh = a.shift + (long long)r * a.n_u * 2;
+    const double inv = a.inv[r], L = a.box[r], dxl = a.dxl[r];
 
     for (int p = 0; p < a.n_snap; ++p) {
         double2 xc = make_double2(0.0, 0.0);
@@ -96,11 +108,13 @@ __global__ __launch_bounds__(kSeriesBS) void k_cg_series(SeriesArgs a) {
             const int slot = (p - l) % a.ring;
             const double xp = rx[slot * kSeriesBS + tid], yp = ry[slot * kSeriesBS + tid];
             const int2 ip = ri[slot * kSeriesBS + tid];
-            const long long cxp = lattice_q(xp, 0.0, inv) + lx * ip.x;
-            const long long cyp = lattice_q(yp, 0.0, inv) + lx * ip.y;
+            const double ox = a.off[2 * (p - l)], oy = a.off[2 * (p - l) + 1];
+            const long long cxp = lattice_q(xp, scaled(ox, dxl), inv) + lx * ip.x;
+            const long long cyp = lattice_q(yp, scaled(oy, dxl), inv) + lx * ip.y;
             for (int t = 0; t < a.n_u; ++t) {
-                const long long vx = (lattice_q(xc.x, sh[2 * t], inv) + lx * ic.x) - cxp;
-                const long long vy = (lattice_q(xc.y, sh[2 * t + 1], inv) + lx * ic.y) - cyp;
+                const double sx = scaled(sum(ox, a.u[2 * t]), dxl), sy = scaled(sum(oy, a.u[2 * t + 1]), dxl);
+                const long long vx = (lattice_q(xc.x, sx, inv) + lx * ic.x) - cxp;
+                const long long vy = (lattice_q(xc.y, sy, inv) + lx * ic.y) - cyp;
                 int idx = MDLG_NQ;
                 if (vx >= -3 && vx <= 3 && vy >= -3 && vy <= 3) idx = c_lut_series.idx[(vy + 3) * 7 + (vx + 3)];
                 int* h = hist + (s * a.n_u + t) * MDLG_NCOUNTS;
@@ -173,7 +187,8 @@ using namespace mdlg;
 extern "C" mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* offsets, const double* box_l,
                                                 const int32_t* lx, int32_t n_snap, const double* pos,
                                                 const int32_t* img, int32_t n_lag, const int32_t* lags, int32_t n_u,
-                                                const double* u, int64_t* counts, double* moments, void* stream) {
+                                                const double* u, const double* offset, int64_t* counts,
+                                                double* moments, void* stream) {
     const char* who = "mdlg_coarse_grain_series: ";
     if (n_rep < 1 || !offsets || !box_l || !lx || !lags || !u || !counts || !pos || !img)
         return fail(MDLG_EINVAL, std::string(who) + "NULL argument or n_rep < 1");
@@ -189,11 +204,17 @@ extern "C" mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* of
     }
     for (int t = 0; t < 2 * n_u; ++t)
         if (!std::isfinite(u[t])) return fail(MDLG_EINVAL, std::string(who) + "u must be finite");
+    std::vector<double> off(2 * (size_t)n_snap, 0.0);
+    if (offset)
+        for (int t = 0; t < 2 * n_snap; ++t) {
+            if (!std::isfinite(offset[t])) return fail(MDLG_EINVAL, std::string(who) + "offsets must be finite");
+            off[t] = offset[t];
+        }
     if (offsets[0] != 0) return fail(MDLG_EINVAL, std::string(who) + "offsets[0] must be 0");
     std::vector<SeriesBlock> blocks;
     std::vector<int> rep_block0(n_rep + 1, 0);
     std::vector<long long> rep_n(n_rep);
-    std::vector<double> inv(n_rep), shift(2 * (size_t)n_rep * n_u);
+    std::vector<double> inv(n_rep), dxl(n_rep);
     for (int r = 0; r < n_rep; ++r) {
         const long long n = offsets[r + 1] - offsets[r];
         if (n < 0) return fail(MDLG_EINVAL, std::string(who) + "offsets must be non-decreasing");
@@ -201,11 +222,7 @@ extern "C" mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* of
         if (!(box_l[r] > 0.0) || !std::isfinite(box_l[r])) return fail(MDLG_EINVAL, std::string(who) + "box_l must be > 0");
         rep_n[r] = n;
         inv[r] = (double)lx[r] / box_l[r];
-        const double dxl = box_l[r] / (double)lx[r];
-        for (int t = 0; t < n_u; ++t) {
-            shift[((size_t)r * n_u + t) * 2] = (u[2 * t] * dxl) * 1.0;
-            shift[((size_t)r * n_u + t) * 2 + 1] = (u[2 * t + 1] * dxl) * 1.0;
-        }
+        dxl[r] = box_l[r] / (double)lx[r];
         rep_block0[r] = (int)blocks.size();
         for (long long s0 = 0; s0 < n; s0 += kSeriesBS)
             blocks.push_back({offsets[r] + s0, (int)(n - s0 < kSeriesBS ? n - s0 : kSeriesBS), r});
@@ -228,8 +245,10 @@ extern "C" mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* of
     const size_t off_lx = (bytes_blocks + 255) / 256 * 256;
     const size_t off_inv = off_lx + ((sizeof(int) * n_rep + 255) / 256 * 256);
     const size_t off_box = off_inv + sizeof(double) * n_rep;
-    const size_t off_shift = off_box + sizeof(double) * n_rep;
-    const size_t off_lags = off_shift + sizeof(double) * shift.size();
+    const size_t off_dxl = off_box + sizeof(double) * n_rep;
+    const size_t off_u = off_dxl + sizeof(double) * n_rep;
+    const size_t off_off = off_u + sizeof(double) * 2 * n_u;
+    const size_t off_lags = off_off + sizeof(double) * off.size();
     const size_t off_b0 = off_lags + sizeof(int) * kSeriesMaxLags;
     const size_t off_rn = (off_b0 + sizeof(int) * (n_rep + 1) + 7) / 8 * 8;
     const size_t off_mp = (off_rn + sizeof(long long) * n_rep + 255) / 256 * 256;
@@ -239,7 +258,9 @@ extern "C" mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* of
     std::memcpy(host.data() + off_lx, lx, sizeof(int) * n_rep);
     std::memcpy(host.data() + off_inv, inv.data(), sizeof(double) * n_rep);
     std::memcpy(host.data() + off_box, box_l, sizeof(double) * n_rep);
-    std::memcpy(host.data() + off_shift, shift.data(), sizeof(double) * shift.size());
+    std::memcpy(host.data() + off_dxl, dxl.data(), sizeof(double) * n_rep);
+    std::memcpy(host.data() + off_u, u, sizeof(double) * 2 * n_u);
+    std::memcpy(host.data() + off_off, off.data(), sizeof(double) * off.size());
     std::memcpy(host.data() + off_lags, lags, sizeof(int) * n_lag);
     std::memcpy(host.data() + off_b0, rep_block0.data(), sizeof(int) * (n_rep + 1));
     std::memcpy(host.data() + off_rn, rep_n.data(), sizeof(long long) * n_rep);
@@ -259,7 +280,9 @@ extern "C" mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* of
     a.lx = (const int*)(dev + off_lx);
     a.inv = (const double*)(dev + off_inv);
     a.box = (const double*)(dev + off_box);
-    a.shift = (const double*)(dev + off_shift);
+    a.dxl = (const double*)(dev + off_dxl);
+    a.u = (const double*)(dev + off_u);
+    a.off = (const double*)(dev + off_off);
     a.lags = (const int*)(dev + off_lags);
     a.counts = (unsigned long long*)counts;
     a.mpart = (double*)(dev + off_mp);

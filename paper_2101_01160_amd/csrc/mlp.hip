@@ -22,10 +22,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kIn = 6, kHid = 256, kOut = 49;
 constexpr long kW1 = 0, kB1 = 1536, kW2 = 1792, kB2 = 67328, kW3 = 67584, kB3 = 133120, kW4 = 133376, kB4 = 145920;
 constexpr long kParams = 145969;
+constexpr int kMaxSplit = 32;
 // fixed input scaling: phi / 0.4, kT / 20, (dt_cg/dx) * 100, |u| / 0.2, cos, sin
 __constant__ float c_scale[kIn] = {2.5f, 0.05f, 100.0f, 5.0f, 1.0f, 1.0f};
 
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2 };
+// Epilogues: STORE C; BIAS_SILU C = z = acc + bias and H = silu(z); BIAS C =
+// acc + bias; SILU_H only H = silu(acc + bias) (inference); SILU_BWD
+// H = acc * silu'(Z) (the backward pass through an activation).
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_SILU_H = 3, EPI_SILU_BWD = 4 };
+// Operand staging modes: 0 element-wise (any strides), 1 contiguous along k,
+// 2 contiguous along the row (A: m, B: n) -- 1 and 2 load 16-byte vectors.
+enum { OP_ANY = 0, OP_K = 1, OP_ROW = 2 };
 
 struct GemmArgs {
     int M, N, K;
@@ -34,50 +41,98 @@ struct GemmArgs {
     const bf16* B;
     long b_sk, b_sn;  // B(k, n) = B[k * b_sk + n * b_sn]
     const float* bias;
-    float* C;  // C[m * ldc + n]
+    float* C;  // C[m * ldc + n] (+ blockIdx.z * split_stride for split-K partials)
     long ldc;
-    bf16* H;  // SiLU output (EPI_BIAS_SILU)
+    bf16* H;  // bf16 output (EPI_BIAS_SILU, EPI_SILU_H, EPI_SILU_BWD)
     long ldh;
+    const float* Z;  // pre-activations read by EPI_SILU_BWD, leading dimension ldh
     int ones_row;  // row m of A reads as all ones (bias gradient row), -1: none
+    int kchunk;    // k range of one split
+    long split_stride;
 };
 
+// Block tile BM x BN, k tile BK (one MFMA step); LDS rows are padded by 8 so
+// that the 16-byte fragment reads of consecutive rows spread over the banks.
 constexpr int BM = 64, BN = 64, BK = 32, LDSK = BK + 8;
 
-// C = A B (+ bias, SiLU).  Block: 256 threads = 4 waves, 64 x 64 outputs;
-// each wave owns 32 x 32 = 2 x 2 MFMA tiles of 16 x 16.  Operands are staged
-// through LDS with k contiguous: As[m][k], Bt[n][k].  MFMA 16x16x32 lane
-// layout: lane l holds A(row l%16, k 8*(l/16) .. +7), B(k 8*(l/16) .. +7,
-// col l%16) and D(rows 4*(l/16) .. +3, col l%16).
-template <int EPI>
+// One thread's share of a 64 x 32 operand tile: 8 values.  For OP_ANY and
+// OP_K the thread owns row r = tid / 4, k = 8 (tid % 4) .. +7; for OP_ROW it
+// owns k = tid / 8 and rows 8 (tid % 8) .. +7.
+template <int MODE>
+__device__ __forceinline__ void load_tile(const bf16* __restrict__ P, long s_row, long s_k, int row0, int rows,
+                                          int rlim, int ones_row, int k0, int kend, bf16x8& v) {
+    const int tid = threadIdx.x;
+    const bf16 zero = (bf16)0.0f, one = (bf16)1.0f;
+    if (MODE == OP_ROW) {
+        const int k = k0 + (tid >> 3), r0 = row0 + (tid & 7) * 8;
+        if (k < kend && r0 + 7 < rlim) {
+            v = *reinterpret_cast<const bf16x8*>(P + k * s_k + r0);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = r0 + e;
+                v[e] = (k < kend && r < rows) ? (r == ones_row ? one : P[r * s_row + k * s_k]) : zero;
+            }
+        }
+    } else {
+        const int r = row0 + (tid >> 2), kk = k0 + (tid & 3) * 8;
+        if (MODE == OP_K && r < rlim && kk + 7 < kend) {
+            v = *reinterpret_cast<const bf16x8*>(P + r * s_row + kk);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = kk + e;
+                v[e] = (r < rows && k < kend) ? (r == ones_row ? one : P[r * s_row + k * s_k]) : zero;
+            }
+        }
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_tile(bf16 (*T)[LDSK], int c0, const bf16x8& v) {
+    const int tid = threadIdx.x;
+    if (MODE == OP_ROW) {
+        const int k = c0 + (tid >> 3), r0 = (tid & 7) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) T[r0 + e][k] = v[e];
+    } else {
+        *reinterpret_cast<bf16x8*>(&T[tid >> 2][c0 + (tid & 3) * 8]) = v;
+    }
+}
+
+// C = A B with a fused epilogue.  Block: 256 threads = 4 waves, 64 x 64
+// outputs; each wave owns 32 x 32 = 2 x 2 MFMA tiles of 16 x 16.  Operands are
+// staged through LDS with k contiguous (As[m][k], Bt[n][k]); the next k tile
+// is loaded into registers while the current one is multiplied.  MFMA
+// 16x16x32 lane layout: lane l holds A(row l%16, k 8*(l/16) .. +7),
+// B(k 8*(l/16) .. +7, col l%16) and D(rows 4*(l/16) .. +3, col l%16).
+// blockIdx.z splits k.
+template <int EPI, int AM, int BMD>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) bf16 As[BM][LDSK];
     __shared__ __attribute__((aligned(16))) bf16 Bt[BN][LDSK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const int kbeg = blockIdx.z * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+    const int mlim = g.ones_row >= 0 ? g.ones_row : g.M;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = tid >> 2, lk = (tid & 3) * 8;  // staging: row / column and 8 k values per thread
-    const bf16 zero = (bf16)0.0f, one = (bf16)1.0f;
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-        {
-            const int m = m0 + lr;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = k0 + lk + e;
-                As[lr][lk + e] = (m < g.M && k < g.K) ? (m == g.ones_row ? one : g.A[m * g.a_sm + k * g.a_sk]) : zero;
-            }
-            const int n = n0 + lr;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = k0 + lk + e;
-                Bt[lr][lk + e] = (n < g.N && k < g.K) ? g.B[k * g.b_sk + n * g.b_sn] : zero;
-            }
-        }
+    bf16x8 ra, rb;
+    load_tile<AM>(g.A, g.a_sm, g.a_sk, m0, g.M, mlim, g.ones_row, kbeg, kend, ra);
+    load_tile<BMD>(g.B, g.b_sn, g.b_sk, n0, g.N, g.N, -1, kbeg, kend, rb);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        store_tile<AM>(As, 0, ra);
+        store_tile<BMD>(Bt, 0, rb);
         __syncthreads();
+        if (k0 + BK < kend) {
+            load_tile<AM>(g.A, g.a_sm, g.a_sk, m0, g.M, mlim, g.ones_row, k0 + BK, kend, ra);
+            load_tile<BMD>(g.B, g.b_sn, g.b_sk, n0, g.N, g.N, -1, k0 + BK, kend, rb);
+        }
         const int kk = (lane >> 4) * 8;
         bf16x8 a[2], b[2];
 #pragma unroll
@@ -90,6 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
+    float* C = g.C + blockIdx.z * g.split_stride;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -100,10 +156,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 const int n = n0 + wn + j * 16 + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
                 float z = acc[i][j][r];
+                if (EPI == EPI_SILU_BWD) {
+                    const float zz = g.Z[m * g.ldh + n];
+                    const float sg = 1.0f / (1.0f + __expf(-zz));
+                    g.H[m * g.ldh + n] = (bf16)(z * sg * (1.0f + zz * (1.0f - sg)));
+                    continue;
+                }
                 if (EPI != EPI_STORE) z += g.bias[n];
-                g.C[m * g.ldc + n] = z;
-                if (EPI == EPI_BIAS_SILU) g.H[m * g.ldh + n] = (bf16)(z / (1.0f + __expf(-z)));
+                if (EPI != EPI_SILU_H) C[m * g.ldc + n] = z;
+                if (EPI == EPI_BIAS_SILU || EPI == EPI_SILU_H) g.H[m * g.ldh + n] = (bf16)(z / (1.0f + __expf(-z)));
             }
+}
+
+// C[m][n] = sum over splits z (in order) of part[z][m][n]
+__global__ void k_splitk_reduce(const float* __restrict__ part, int splits, int M, int N, float* __restrict__ C,
+                                long ldc) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long mn = (long)M * N;
+    if (i >= mn) return;
+    float v[8];
+    float s = 0.f;
+    for (int z0 = 0; z0 < splits; z0 += 8) {
+        const int nz = min(8, splits - z0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = e < nz ? part[(long)(z0 + e) * mn + i] : 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += v[e];
+    }
+    C[(i / N) * ldc + i % N] = s;
 }
 
 __global__ void k_prep_input(const float* __restrict__ x, int B, bf16* __restrict__ xb) {
@@ -111,41 +191,42 @@ __global__ void k_prep_input(const float* __restrict__ x, int B, bf16* __restric
     if (i < B * kIn) xb[i] = (bf16)(x[i] * c_scale[i % kIn]);
 }
 
-// Per sample: q = softmax(z); with a target R: loss_b = sum_i R_i (log R_i - log q_i)
-// and the logit gradient G = (q sum_i R_i - R) / B (bf16, for the backward products).
-__global__ void k_softmax(const float* __restrict__ z, const float* __restrict__ R, int B, float* __restrict__ q,
-                          bf16* __restrict__ G, float* __restrict__ loss_b) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const float* zb = z + (long)b * kOut;
-    float mx = zb[0];
-    for (int i = 1; i < kOut; ++i) mx = fmaxf(mx, zb[i]);
-    float s = 0.f;
-    for (int i = 0; i < kOut; ++i) s += __expf(zb[i] - mx);
-    const float ls = __logf(s);
-    float loss = 0.f, rs = 0.f;
-    if (R)
-        for (int i = 0; i < kOut; ++i) rs += R[(long)b * kOut + i];
-    for (int i = 0; i < kOut; ++i) {
-        const float logq = zb[i] - mx - ls;
-        const float qi = __expf(logq);
-        if (q) q[(long)b * kOut + i] = qi;
-        if (R) {
-            const float ri = R[(long)b * kOut + i];
-            if (ri > 0.f) loss += ri * (__logf(ri) - logq);
-            G[(long)b * kOut + i] = (bf16)((qi * rs - ri) / (float)B);
-        }
-    }
-    if (R) loss_b[b] = loss;
+__device__ __forceinline__ float wave_max_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
-// G = dH * silu'(Z), silu'(z) = s (1 + z (1 - s)), s = 1 / (1 + e^-z)
-__global__ void k_silu_bwd(const float* __restrict__ dH, const float* __restrict__ Z, long n, bf16* __restrict__ G) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float z = Z[i];
-    const float s = 1.0f / (1.0f + __expf(-z));
-    G[i] = (bf16)(dH[i] * s * (1.0f + z * (1.0f - s)));
+// One wave per sample, lane i < 49 holds logit i: q = softmax(z); with a
+// target R the per-sample loss sum_i R_i (log R_i - log q_i) and the logit
+// gradient G = (q sum_i R_i - R) / B (bf16, for the backward products).  The
+// block's four losses are summed in order into loss_part[block].
+__global__ __launch_bounds__(256) void k_softmax(const float* __restrict__ z, const float* __restrict__ R, int B,
+                                                 float* __restrict__ q, bf16* __restrict__ G,
+                                                 float* __restrict__ loss_part) {
+    __shared__ float wl[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = blockIdx.x * 4 + w;
+    const bool on = b < B && lane < kOut;
+    const long o = (long)b * kOut + lane;
+    const float zi = on ? z[o] : -INFINITY;
+    const float mx = wave_max_f(zi);
+    const float ei = on ? __expf(zi - mx) : 0.f;
+    const float ls = __logf(wave_sum_f(ei));
+    const float logq = zi - mx - ls;
+    const float qi = on ? __expf(logq) : 0.f;
+    if (on && q) q[o] = qi;
+    if (!R) return;
+    const float ri = on ? R[o] : 0.f;
+    const float rs = wave_sum_f(ri);
+    const float li = wave_sum_f(on && ri > 0.f ? ri * (__logf(ri) - logq) : 0.f);
+    if (on) G[o] = (bf16)((qi * rs - ri) / (float)B);
+    if (lane == 0) wl[w] = b < B ? li : 0.f;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = (wl[0] + wl[1]) + (wl[2] + wl[3]);
 }
 
 __global__ void k_sum(const float* __restrict__ a, int n, float scale, float* out) {
@@ -161,10 +242,31 @@ __global__ void k_sum(const float* __restrict__ a, int n, float scale, float* ou
     if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
-// Adam on the fp32 master weights, then the bf16 copies the products read.
+// Position of parameter i in the transposed weight copy (W_l [fin][fout]
+// stored as [fout][fin] at the same offset), or -1 for a bias.
+__device__ __forceinline__ long transposed_pos(long i) {
+    long o = 0, fin = 0, fout = 0;
+    if (i < kB1) {
+        o = kW1, fin = kIn, fout = kHid;
+    } else if (i >= kW2 && i < kB2) {
+        o = kW2, fin = kHid, fout = kHid;
+    } else if (i >= kW3 && i < kB3) {
+        o = kW3, fin = kHid, fout = kHid;
+    } else if (i >= kW4 && i < kB4) {
+        o = kW4, fin = kHid, fout = kOut;
+    } else {
+        return -1;
+    }
+    const long r = i - o;
+    return o + (r % fout) * fin + r / fout;
+}
+
+// Adam on the fp32 master weights, then the bf16 copies the products read:
+// wb in the parameter layout (backward products), wt with every weight
+// matrix transposed (forward products, whose k then runs contiguously).
 __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, long n, float lr, float b1, float b2, float eps, float bc1,
-                       float bc2, bf16* __restrict__ wb) {
+                       float bc2, bf16* __restrict__ wb, bf16* __restrict__ wt) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -175,11 +277,16 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __re
     const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
     w[i] = wi;
     wb[i] = (bf16)wi;
+    const long t = transposed_pos(i);
+    if (t >= 0) wt[t] = (bf16)wi;
 }
 
-__global__ void k_to_bf16(const float* __restrict__ w, long n, bf16* __restrict__ wb) {
+__global__ void k_to_bf16(const float* __restrict__ w, long n, bf16* __restrict__ wb, bf16* __restrict__ wt) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) wb[i] = (bf16)w[i];
+    if (i >= n) return;
+    wb[i] = (bf16)w[i];
+    const long t = transposed_pos(i);
+    if (t >= 0) wt[t] = (bf16)w[i];
 }
 
 }  // namespace
@@ -194,59 +301,112 @@ struct mdlg_mlp {
     float* m = nullptr;   // Adam moments
     float* v = nullptr;
     float* grad = nullptr;
-    bf16* wb = nullptr;   // bf16 copies
+    bf16* wb = nullptr;   // bf16 copies: parameter layout
+    bf16* wt = nullptr;   // and weight matrices transposed
     bf16* xb = nullptr;
     float* Z[3] = {nullptr, nullptr, nullptr};
     bf16* H[3] = {nullptr, nullptr, nullptr};
     float* z4 = nullptr;
-    float* q = nullptr;
     bf16* g4 = nullptr;
-    float* dh = nullptr;
-    bf16* gh = nullptr;
+    bf16* gh[2] = {nullptr, nullptr};  // activation gradients, ping-pong
     float* loss_b = nullptr;
     float* loss = nullptr;
+    float* ws = nullptr;  // split-k partials of the weight gradients
     float* x1 = nullptr;  // one-sample staging for the surrogate call
     float* g1 = nullptr;
 };
 
 namespace {
 
-hipError_t gemm(int epi, int M, int N, int K, const bf16* A, long a_sm, long a_sk, const bf16* B, long b_sk, long b_sn,
-                const float* bias, float* C, long ldc, bf16* H, long ldh, hipStream_t st, int ones_row = -1) {
-    GemmArgs g{M, N, K, A, a_sm, a_sk, B, b_sk, b_sn, bias, C, ldc, H, ldh, ones_row};
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-    if (epi == EPI_STORE)
-        hipLaunchKernelGGL(k_gemm<EPI_STORE>, grid, dim3(256), 0, st, g);
-    else if (epi == EPI_BIAS_SILU)
-        hipLaunchKernelGGL(k_gemm<EPI_BIAS_SILU>, grid, dim3(256), 0, st, g);
+template <int EPI, int AM>
+void launch_b(int bm, dim3 grid, hipStream_t st, const GemmArgs& g) {
+    if (bm == OP_K)
+        hipLaunchKernelGGL((k_gemm<EPI, AM, OP_K>), grid, dim3(256), 0, st, g);
+    else if (bm == OP_ROW)
+        hipLaunchKernelGGL((k_gemm<EPI, AM, OP_ROW>), grid, dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL(k_gemm<EPI_BIAS>, grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((k_gemm<EPI, AM, OP_ANY>), grid, dim3(256), 0, st, g);
+}
+
+template <int EPI>
+void launch_ab(int am, int bm, dim3 grid, hipStream_t st, const GemmArgs& g) {
+    if (am == OP_K)
+        launch_b<EPI, OP_K>(bm, grid, st, g);
+    else if (am == OP_ROW)
+        launch_b<EPI, OP_ROW>(bm, grid, st, g);
+    else
+        launch_b<EPI, OP_ANY>(bm, grid, st, g);
+}
+
+// staging mode of an operand with element strides (s_row, s_k)
+int op_mode(const bf16* p, long s_row, long s_k) {
+    const bool aligned = ((uintptr_t)p & 15) == 0;
+    if (aligned && s_k == 1 && s_row % 8 == 0) return OP_K;
+    if (aligned && s_row == 1 && s_k % 8 == 0) return OP_ROW;
+    return OP_ANY;
+}
+
+// C = A B with the epilogue epi.  Long-k products (the weight gradients, k =
+// batch) are split over blockIdx.z into partials in `ws` (room for
+// max_split x M x N floats) and summed in a fixed order.
+hipError_t gemm(int epi, int M, int N, int K, const bf16* A, long a_sm, long a_sk, const bf16* B, long b_sk, long b_sn,
+                const float* bias, float* C, long ldc, bf16* H, long ldh, hipStream_t st, int ones_row = -1,
+                float* ws = nullptr, int max_split = 1, const float* Z = nullptr) {
+    const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+    int split = 1;
+    if (epi == EPI_STORE && ws && max_split > 1) {
+        // about one block per compute unit, at least eight k tiles per split
+        while (split * 2 <= max_split && tiles * split < 256 && K / (split * 2) >= 8 * BK) split *= 2;
+    }
+    const int kchunk = ((K + split - 1) / split + BK - 1) / BK * BK;
+    GemmArgs g{M, N, K, A, a_sm, a_sk, B, b_sk, b_sn, bias, C, ldc, H, ldh, Z, ones_row, kchunk, 0};
+    if (split > 1) {
+        g.C = ws;
+        g.ldc = N;
+        g.split_stride = (long)M * N;
+    }
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, split);
+    const int am = op_mode(A, a_sm, a_sk), bm = op_mode(B, b_sn, b_sk);
+    switch (epi) {
+        case EPI_STORE: launch_ab<EPI_STORE>(am, bm, grid, st, g); break;
+        case EPI_BIAS_SILU: launch_ab<EPI_BIAS_SILU>(am, bm, grid, st, g); break;
+        case EPI_BIAS: launch_ab<EPI_BIAS>(am, bm, grid, st, g); break;
+        case EPI_SILU_H: launch_ab<EPI_SILU_H>(am, bm, grid, st, g); break;
+        default: launch_ab<EPI_SILU_BWD>(am, bm, grid, st, g); break;
+    }
+    if (split > 1) {
+        hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(((long)M * N + 255) / 256)), dim3(256), 0, st,
+                           (const float*)ws, split, M, N, C, ldc);
+    }
     return hipGetLastError();
 }
 
 unsigned nblk(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-// Forward pass on B inputs already in m->xb; leaves z1..z3, h1..h3, z4 and q.
-hipError_t forward(mdlg_mlp* m, int B, hipStream_t st) {
+// Forward pass on B inputs already in m->xb; leaves h1..h3 and the logits z4,
+// and for training (keep_z) the pre-activations z1..z3.
+hipError_t forward(mdlg_mlp* m, int B, bool keep_z, hipStream_t st) {
     const long in[4] = {kIn, kHid, kHid, kHid};
     const long wo[4] = {kW1, kW2, kW3, kW4};
     const long bo[4] = {kB1, kB2, kB3, kB4};
     hipError_t e = hipSuccess;
     const bf16* a = m->xb;
     for (int l = 0; l < 3 && e == hipSuccess; ++l) {
-        e = gemm(EPI_BIAS_SILU, B, kHid, (int)in[l], a, in[l], 1, m->wb + wo[l], kHid, 1, m->w + bo[l], m->Z[l], kHid,
-                 m->H[l], kHid, st);
+        e = gemm(keep_z ? EPI_BIAS_SILU : EPI_SILU_H, B, kHid, (int)in[l], a, in[l], 1, m->wt + wo[l], 1, in[l],
+                 m->w + bo[l], m->Z[l], kHid, m->H[l], kHid, st);
         a = m->H[l];
     }
     if (e == hipSuccess)
-        e = gemm(EPI_BIAS, B, kOut, kHid, a, kHid, 1, m->wb + wo[3], kOut, 1, m->w + bo[3], m->z4, kOut, nullptr, 0, st);
+        e = gemm(EPI_BIAS, B, kOut, kHid, a, kHid, 1, m->wt + wo[3], 1, kHid, m->w + bo[3], m->z4, kOut, nullptr, 0, st);
     return e;
 }
 
 // Loss and gradient into m->grad (and m->loss) for targets R.
 hipError_t backward(mdlg_mlp* m, const float* R, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_softmax, dim3(nblk(B)), dim3(256), 0, st, (const float*)m->z4, R, B, m->q, m->g4, m->loss_b);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, (const float*)m->loss_b, B, 1.0f / B, m->loss);
+    const int sb = (B + 3) / 4;
+    hipLaunchKernelGGL(k_softmax, dim3(sb), dim3(256), 0, st, (const float*)m->z4, R, B, (float*)nullptr, m->g4,
+                       m->loss_b);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, (const float*)m->loss_b, sb, 1.0f / B, m->loss);
     hipError_t e = hipGetLastError();
     // Weight and bias gradients come from one product [prev | 1]^T G: the bias
     // of each layer directly follows its weights in the parameter vector, so
@@ -254,22 +414,24 @@ hipError_t backward(mdlg_mlp* m, const float* R, int B, hipStream_t st) {
     // layer 4: [dW4; db4] = [H3 | 1]^T G4, dH3 = G4 W4^T
     if (e == hipSuccess)
         e = gemm(EPI_STORE, kHid + 1, kOut, B, m->H[2], 1, kHid, m->g4, kOut, 1, nullptr, m->grad + kW4, kOut, nullptr, 0,
-                 st, kHid);
+                 st, kHid, m->ws, kMaxSplit);
+    // G3 = (G4 W4^T) * silu'(z3), fused into the product's epilogue
     if (e == hipSuccess)
-        e = gemm(EPI_STORE, B, kHid, kOut, m->g4, kOut, 1, m->wb + kW4, 1, kOut, nullptr, m->dh, kHid, nullptr, 0, st);
+        e = gemm(EPI_SILU_BWD, B, kHid, kOut, m->g4, kOut, 1, m->wb + kW4, 1, kOut, nullptr, nullptr, 0, m->gh[0], kHid,
+                 st, -1, nullptr, 1, m->Z[2]);
     const long wo[3] = {kW1, kW2, kW3};
+    int cur = 0;
     for (int l = 2; l >= 0 && e == hipSuccess; --l) {
-        hipLaunchKernelGGL(k_silu_bwd, dim3(nblk((long)B * kHid)), dim3(256), 0, st, (const float*)m->dh,
-                           (const float*)m->Z[l], (long)B * kHid, m->gh);
         const bf16* prev = l > 0 ? m->H[l - 1] : m->xb;
         const int fin = l > 0 ? kHid : kIn;
         // [dW; db] = [prev | 1]^T G
-        e = gemm(EPI_STORE, fin + 1, kHid, B, prev, 1, fin, m->gh, kHid, 1, nullptr, m->grad + wo[l], kHid, nullptr, 0, st,
-                 fin);
-        // dH_prev = G W^T (not needed below the first layer)
+        e = gemm(EPI_STORE, fin + 1, kHid, B, prev, 1, fin, m->gh[cur], kHid, 1, nullptr, m->grad + wo[l], kHid, nullptr,
+                 0, st, fin, m->ws, kMaxSplit);
+        // G_prev = (G W^T) * silu'(z_prev) (not needed below the first layer)
         if (e == hipSuccess && l > 0)
-            e = gemm(EPI_STORE, B, kHid, kHid, m->gh, kHid, 1, m->wb + wo[l], 1, kHid, nullptr, m->dh, kHid, nullptr, 0,
-                     st);
+            e = gemm(EPI_SILU_BWD, B, kHid, kHid, m->gh[cur], kHid, 1, m->wb + wo[l], 1, kHid, nullptr, nullptr, 0,
+                     m->gh[1 - cur], kHid, st, -1, nullptr, 1, m->Z[l - 1]);
+        cur = 1 - cur;
     }
     if (e == hipSuccess) e = hipGetLastError();
     return e;
@@ -291,8 +453,8 @@ mdlg_status check_batch(const mdlg_mlp* m, int B, const char* who) {
 
 extern "C" void mdlg_mlp_destroy(mdlg_mlp* m) {
     if (!m) return;
-    void* p[] = {m->w, m->m, m->v, m->grad, m->wb, m->xb, m->Z[0], m->Z[1], m->Z[2], m->H[0], m->H[1], m->H[2],
-                 m->z4, m->q, m->g4, m->dh, m->gh, m->loss_b, m->loss, m->x1, m->g1};
+    void* p[] = {m->w, m->m, m->v, m->grad, m->wb, m->wt, m->xb, m->Z[0], m->Z[1], m->Z[2], m->H[0], m->H[1], m->H[2],
+                 m->z4, m->g4, m->gh[0], m->gh[1], m->loss_b, m->loss, m->ws, m->x1, m->g1};
     for (void* q : p)
         if (q) (void)hipFree(q);
     delete m;
@@ -317,14 +479,15 @@ extern "C" mdlg_status mdlg_mlp_create(mdlg_mlp** out, const float* params, int3
     take(dalloc(&m->v, kParams));
     take(dalloc(&m->grad, kParams));
     take(dalloc(&m->wb, kParams));
+    take(dalloc(&m->wt, kParams));
     take(dalloc(&m->xb, B * kIn));
     take(dalloc(&m->z4, B * kOut));
-    take(dalloc(&m->q, B * kOut));
     take(dalloc(&m->g4, B * kOut));
-    take(dalloc(&m->dh, B * kHid));
-    take(dalloc(&m->gh, B * kHid));
-    take(dalloc(&m->loss_b, B));
+    take(dalloc(&m->gh[0], B * kHid));
+    take(dalloc(&m->gh[1], B * kHid));
+    take(dalloc(&m->loss_b, (B + 3) / 4));
     take(dalloc(&m->loss, 1));
+    take(dalloc(&m->ws, (size_t)kMaxSplit * (kHid + 1) * kHid));
     take(dalloc(&m->x1, kIn));
     take(dalloc(&m->g1, kOut));
     for (int l = 0; l < 3; ++l) {
@@ -339,7 +502,7 @@ extern "C" mdlg_status mdlg_mlp_create(mdlg_mlp** out, const float* params, int3
     if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, sizeof(float) * kParams, st);
     if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, sizeof(float) * kParams, st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_to_bf16, dim3(nblk(kParams)), dim3(256), 0, st, (const float*)m->w, kParams, m->wb);
+        hipLaunchKernelGGL(k_to_bf16, dim3(nblk(kParams)), dim3(256), 0, st, (const float*)m->w, kParams, m->wb, m->wt);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -365,9 +528,9 @@ extern "C" mdlg_status mdlg_mlp_forward(mdlg_mlp* m, const float* x, int32_t B, 
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_prep_input, dim3(nblk((long)B * kIn)), dim3(256), 0, st, x, B, m->xb);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward(m, B, st);
+    if (e == hipSuccess) e = forward(m, B, false, st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_softmax, dim3(nblk(B)), dim3(256), 0, st, (const float*)m->z4, (const float*)nullptr, B,
+        hipLaunchKernelGGL(k_softmax, dim3((B + 3) / 4), dim3(256), 0, st, (const float*)m->z4, (const float*)nullptr, B,
                            g_out, (bf16*)nullptr, (float*)nullptr);
         e = hipGetLastError();
     }
@@ -383,7 +546,7 @@ extern "C" mdlg_status mdlg_mlp_gradient(mdlg_mlp* m, const float* x, const floa
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_prep_input, dim3(nblk((long)B * kIn)), dim3(256), 0, st, x, B, m->xb);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward(m, B, st);
+    if (e == hipSuccess) e = forward(m, B, true, st);
     if (e == hipSuccess) e = backward(m, target, B, st);
     if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && grad) e = hipMemcpyAsync(grad, m->grad, sizeof(float) * kParams, hipMemcpyDeviceToDevice, st);
@@ -400,14 +563,14 @@ extern "C" mdlg_status mdlg_mlp_train_step(mdlg_mlp* m, const float* x, const fl
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_prep_input, dim3(nblk((long)B * kIn)), dim3(256), 0, st, x, B, m->xb);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward(m, B, st);
+    if (e == hipSuccess) e = forward(m, B, true, st);
     if (e == hipSuccess) e = backward(m, target, B, st);
     if (e == hipSuccess) {
         m->step += 1;
         const float b1 = 0.9f, b2 = 0.999f;
         const float bc1 = 1.0f - std::pow(b1, (float)m->step), bc2 = 1.0f - std::pow(b2, (float)m->step);
         hipLaunchKernelGGL(k_adam, dim3(nblk(kParams)), dim3(256), 0, st, m->w, m->m, m->v, (const float*)m->grad,
-                           kParams, lr, b1, b2, 1e-8f, bc1, bc2, m->wb);
+                           kParams, lr, b1, b2, 1e-8f, bc1, bc2, m->wb, m->wt);
         e = hipGetLastError();
     }
     if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToDevice, st);

@@ -1,6 +1,7 @@
 """GPU parity of the trajectory coarse-graining for many lags and drifts
-(mdlg_coarse_grain_series) with the oracle's single-event coarse-graining
-summed over every snapshot pair: counts bit-exact, moments within 1e-12."""
+(mdlg_coarse_grain_series) with the oracle's single-event coarse-graining on
+the translated lattice of each pair, summed over every snapshot pair: counts
+bit-exact, moments within 1e-12."""
 import math
 
 import numpy as np
@@ -29,8 +30,9 @@ def walk(n, L, P, step, seed):
     return np.stack(xs), np.stack(imgs)
 
 
-def reference(specs, xs, imgs, lags, us):
-    """Sum of oracle events (k_prev = 0, k_cur = 1) over all pairs (p - l, p)."""
+def reference(specs, xs, imgs, lags, us, offs=None):
+    """Sum of oracle events over all pairs (p - l, p): lattice shifted by o dx
+    and (o + u) dx, o = offs[p - l]."""
     P = xs.shape[0]
     off = 0
     counts = np.zeros((len(specs), len(lags), len(us), 50), dtype=np.int64)
@@ -43,15 +45,18 @@ def reference(specs, xs, imgs, lags, us):
         for s, l in enumerate(lags):
             for t, u in enumerate(us):
                 m = np.zeros(5)
+                dxl = L / lx
                 for p in range(l, P):
-                    omd.coarse_grain(lx, L, xs[p - l, sl], xs[p, sl], imgs[p - l, sl], imgs[p, sl], 0, 1, u,
-                                     counts=counts[r, s, t], moments=m)
+                    o = np.zeros(2) if offs is None else np.asarray(offs[p - l], dtype=np.float64)
+                    uu = np.asarray(u, dtype=np.float64)
+                    omd.coarse_grain_shift(lx, L, xs[p - l, sl], xs[p, sl], imgs[p - l, sl], imgs[p, sl],
+                                           o * dxl, (o + uu) * dxl, counts=counts[r, s, t], moments=m)
                 if t == 0:
                     moments[r, s] = m
     return counts, moments
 
 
-def run(specs, lags, us, P, seed=0, repeat=1):
+def run(specs, lags, us, P, seed=0, repeat=1, offs=None):
     import torch
 
     import paper_2101_01160_amd as m
@@ -69,26 +74,28 @@ def run(specs, lags, us, P, seed=0, repeat=1):
     img = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
     for _ in range(repeat):
         m.mdlg_coarse_grain_series(offsets, [s[1] for s in specs], [s[2] for s in specs], pos, img, lags, us,
-                                   counts, moments)
+                                   counts, moments, lattice_offset=offs)
     torch.cuda.synchronize()
     return xs, imgs, counts.cpu().numpy(), moments.cpu().numpy()
 
 
-def check(specs, lags, us, P, seed=0):
-    print(f"cg_series specs={specs} lags={lags} n_u={len(us)} P={P}", flush=True)
-    xs, imgs, c, mo = run(specs, lags, us, P, seed)
-    rc, rm = reference(specs, xs, imgs, lags, us)
+def check(specs, lags, us, P, seed=0, offs=None):
+    print(f"cg_series specs={specs} lags={lags} n_u={len(us)} P={P} offsets={offs is not None}", flush=True)
+    xs, imgs, c, mo = run(specs, lags, us, P, seed, offs=offs)
+    rc, rm = reference(specs, xs, imgs, lags, us, offs)
     assert np.array_equal(c, rc)
     scale = np.maximum(1.0, np.abs(rm).max())
     assert np.allclose(mo, rm, rtol=1e-12, atol=1e-12 * scale)
     return c
 
 
-def test_series_matches_summed_events():
+@pytest.mark.parametrize("with_offsets", [False, True])
+def test_series_matches_summed_events(with_offsets):
     specs = [(300, 30.0, 15, 0.4), (129, 20.0, 10, 0.9), (0, 10.0, 5, 0.1), (200, 17.3, 5, 3.0)]
     lags = [1, 2, 5, 7]
     us = [(0.0, 0.0), (0.13, -0.07), (-0.2, 0.19)]
-    c = check(specs, lags, us, P=9)
+    offs = np.random.default_rng(9).uniform(0.0, 1.0, (9, 2)) if with_offsets else None
+    c = check(specs, lags, us, P=9, offs=offs)
     # the large steps of the last replica reach the overflow bin
     assert c[3, :, :, 49].sum() > 0
     # every particle lands in one bin per pair
@@ -103,7 +110,7 @@ def test_series_largest_configuration():
     lags = list(range(1, 33))
     rng = np.random.default_rng(1)
     us = [tuple(v) for v in rng.uniform(-0.2, 0.2, (8, 2))]
-    check(specs, lags, us, P=34, seed=5)
+    check(specs, lags, us, P=34, seed=5, offs=rng.uniform(-2.0, 2.0, (34, 2)))
 
 
 def test_series_accumulates():

@@ -140,3 +140,47 @@ def test_frame_shift_is_a_galilean_boost():
     xs1[:, 0] += 0.5 * dxl
     ref, _, _ = md.coarse_grain(lx, L, xs0, xs1, None, img, 0, 1)
     assert np.array_equal(c_half, ref)
+
+
+def _offset_grid(M, lx):
+    """Particles at every in-cell offset (i/M, j/M) of every cell (dx = 1): exact binary fractions."""
+    o = np.arange(M) / M
+    c = np.arange(lx)
+    x = (c[:, None] + o[None, :]).ravel()
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+@pytest.mark.parametrize("s", [(0.0, 0.0), (0.125, 0.0), (0.625, 0.375), (3.5, 1.875)])
+def test_translated_lattice_counts_crossing_fraction(s):
+    # rigid displacement (3/8, 0) cells: exactly 3/8 of uniformly spread particles
+    # cross one cell boundary, whatever the lattice origin
+    lx, M = 6, 8
+    p0 = _offset_grid(M, lx)
+    p1 = p0 + np.array([3 / 8, 0.0])
+    img1 = np.zeros(p1.shape, dtype=np.int64)
+    img1[p1[:, 0] >= lx, 0] = 1
+    p1[p1[:, 0] >= lx, 0] -= lx
+    c, _ = md.coarse_grain_shift(lx, float(lx), p0, p1, np.zeros_like(img1), img1, s, s)
+    n = p0.shape[0]
+    v = lattice.d2q49()
+    i10 = int(np.flatnonzero((v[:, 0] == 1) & (v[:, 1] == 0))[0])
+    assert c[i10] * 8 == 3 * n
+    assert c[0] * 8 == 5 * n
+    assert c.sum() == n
+
+
+def test_shift_difference_acts_as_drift():
+    # a later lattice shifted by u dx = (1/4, -1/8) relative to the earlier one,
+    # particles at rest: the fractions 1/4 and 1/8 see velocities +1 in x and -1 in y
+    lx, M = 5, 8
+    p = _offset_grid(M, lx)
+    z = np.zeros(p.shape, dtype=np.int64)
+    c, _ = md.coarse_grain_shift(lx, float(lx), p, p, z, z, (0.5, 0.25), (0.75, 0.125))
+    n = p.shape[0]
+    v = lattice.d2q49()
+    idx = {tuple(v[i]): i for i in range(49)}
+    assert c[idx[(1, 0)]] * 32 == n * (1 * 7)    # x crosses (1/4), y does not (7/8)
+    assert c[idx[(0, -1)]] * 32 == n * (3 * 1)   # x stays (3/4), y crosses (1/8)
+    assert c[idx[(1, -1)]] * 32 == n * (1 * 1)
+    assert c[idx[(0, 0)]] * 32 == n * (3 * 7)
