@@ -152,12 +152,14 @@ mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream);
  * cell-list interval) is replayed as three graphs with HIP events on
  * `stream` between them: the cell rebuild, the ordinary steps before the
  * unit's first coarse-graining step, and the remaining steps.  ms_out (host
- * [3]) receives the average device time of [0] one ordinary step kernel (the
- * middle graph's time over its steps), [1] one coarse-graining step with its
- * reduction (the last graph's time less its ordinary steps), [2] one cell
- * rebuild; n_out (host [3], may be NULL) the number of kernels or graphs
- * behind each average.  The first two units warm up (graph capture leaves
- * the GPU idle) and are not averaged; nunits >= 3.  Synchronises `stream`. */
+ * [3]) receives the device time per launch of [0] an ordinary step kernel
+ * (the ordinary steps' graph time over their number), [1] a coarse-graining
+ * step with its reduction (the last graph's time less its ordinary steps)
+ * and [2] a cell rebuild, each averaged over the counted units; n_out (host
+ * [3], may be NULL) the number of kernels or graphs behind each.  The graphs
+ * stay in the handle for later calls; units up to the last one whose graphs
+ * were captured in this call warm up (capture leaves the GPU idle) and are
+ * not counted.  nunits >= 3.  Synchronises `stream`. */
 mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_out, int32_t* n_out, void* stream);
 
 /* Copy the state out in the caller's particle order (index = position in

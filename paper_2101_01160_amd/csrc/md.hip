@@ -1325,6 +1325,12 @@ struct lj_md {
     long long* d_event_k = nullptr;
     hipStream_t cap = nullptr;
     std::map<GraphKey, GraphVal> graphs;
+    // graphs of lj_md_step_timed: rebuild | ordinary steps | rest of a unit
+    struct TimedGraphs {
+        std::array<hipGraphExec_t, 3> g;
+        int M, tail_events;
+    };
+    std::map<std::tuple<int, int, int, int>, TimedGraphs> tgraphs;
     bool use_graphs = true;
 };
 
@@ -1333,6 +1339,10 @@ namespace {
 void clear_graphs(lj_md* md) {
     for (auto& kv : md->graphs) (void)hipGraphExecDestroy(kv.second.exec);
     md->graphs.clear();
+    for (auto& kv : md->tgraphs)
+        for (auto x : kv.second.g)
+            if (x) (void)hipGraphExecDestroy(x);
+    md->tgraphs.clear();
 }
 
 #define EXT_LAUNCH(KERNEL, BSV, GRIDV) \
@@ -1926,18 +1936,15 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
         std::array<int, 4> ev;
         int M, tail_events;
     };
-    struct Graphs {
-        std::array<hipGraphExec_t, 3> g;
-        int M, tail_events;
-    };
-    std::vector<hipGraphExec_t> made;
-    std::map<std::tuple<int, int, int>, Graphs> cache;
+    using Graphs = lj_md::TimedGraphs;
+    auto& cache = md->tgraphs;
+    int last_capture = -1;  // index of the last unit whose graphs were captured in this call
     std::vector<hipEvent_t> evs;
     std::vector<UnitRec> order;
     mdlg_status status = MDLG_OK;
     for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
         const int phase = md->cg_on ? (int)(md->cg_t % md->s_cg) : -1;
-        const auto key = std::make_tuple(md->ppar, md->opar, phase);
+        const auto key = std::make_tuple(K, md->ppar, md->opar, phase);
         auto it = cache.find(key);
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
         Graphs G{{nullptr, nullptr, nullptr}, K, 0};
@@ -1972,13 +1979,16 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                     return e;
                 }, &G.g[2]);
             G.tail_events = (int)(md->events - ev0);
-            for (auto x : G.g)
-                if (x) made.push_back(x);
-            if (status != MDLG_OK) break;
+            if (status != MDLG_OK) {
+                for (auto x : G.g)
+                    if (x) (void)hipGraphExecDestroy(x);
+                break;
+            }
             cache[key] = G;
+            last_capture = (int)u;
             // captures only recorded work: restore the step counters
-            md->ppar = std::get<0>(key);
-            md->opar = std::get<1>(key);
+            md->ppar = std::get<1>(key);
+            md->opar = std::get<2>(key);
             md->steps_done = steps0;
             md->cg_t = cg_t0;
             md->events = ev0;
@@ -2020,11 +2030,15 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     hipError_t e = hipStreamSynchronize(st);
     if (status == MDLG_OK && e != hipSuccess) status = fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
     if (status == MDLG_OK) {
-        // the first two units run right after the graphs were captured on the
-        // host (the GPU idled meanwhile): they warm up and are not averaged
-        double sum_plain = 0.0, sum_tail = 0.0, sum_rebuild = 0.0;
-        long long n_plain = 0, n_tail_plain = 0, n_events = 0, n_rebuild = 0;
-        for (size_t ui = order.size() > 2 ? 2 : 0; ui < order.size(); ++ui) {
+        // units up to the last capture of this call ran while the host captured
+        // graphs (the GPU idled meanwhile): they warm up and are not counted.
+        // The later units' times are summed, and each total divided by the
+        // number of kernels (or graphs) behind it: averages per launch.
+        double sum_plain = 0.0, sum_event = 0.0, sum_rebuild = 0.0;
+        long long n_plain = 0, n_events = 0, n_rebuild = 0, n_tail_plain = 0;
+        size_t first = last_capture >= 0 ? (size_t)last_capture + 1 : 0;
+        if (first >= order.size()) first = order.size() - 1;
+        for (size_t ui = first; ui < order.size(); ++ui) {
             const UnitRec& rec = order[ui];
             float t[3] = {0, 0, 0};
             for (int q = 0; q < 3; ++q) (void)hipEventElapsedTime(&t[q], evs[rec.ev[q]], evs[rec.ev[q + 1]]);
@@ -2033,7 +2047,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
             sum_plain += t[1];
             n_plain += rec.M;
             if (rec.tail_events > 0) {
-                sum_tail += t[2];
+                sum_event += t[2];
                 n_events += rec.tail_events;
                 n_tail_plain += K - rec.M - rec.tail_events;
             } else {
@@ -2041,18 +2055,17 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                 n_plain += K - rec.M;
             }
         }
-        const double plain = n_plain ? sum_plain / n_plain : 0.0;
-        // the tails' ordinary steps are priced at the average of the ordinary steps
+        const double plain = n_plain ? sum_plain / (double)n_plain : 0.0;
+        // the tails' ordinary steps are priced at the average ordinary step
         ms_out[0] = plain;
-        ms_out[1] = n_events ? (sum_tail - (double)n_tail_plain * plain) / n_events : 0.0;
-        ms_out[2] = n_rebuild ? sum_rebuild / n_rebuild : 0.0;
+        ms_out[1] = n_events ? (sum_event - (double)n_tail_plain * plain) / (double)n_events : 0.0;
+        ms_out[2] = n_rebuild ? sum_rebuild / (double)n_rebuild : 0.0;
         if (n_out) {
             n_out[0] = (int32_t)n_plain;
             n_out[1] = (int32_t)n_events;
             n_out[2] = (int32_t)n_rebuild;
         }
     }
-    for (auto x : made) (void)hipGraphExecDestroy(x);
     for (auto x : evs) (void)hipEventDestroy(x);
     return status;
 }
