@@ -237,21 +237,23 @@ mdlg_status mdlg_coarse_grain(const mdlg_lattice* lat, double box_l, int64_t n,
  * holds n_rep replicas; replica r owns particles offsets[r] .. offsets[r+1]-1
  * (host [n_rep + 1], offsets[0] = 0) in a box of side box_l[r] (host) with an
  * lx[r] x lx[r] lattice (host).  pos (device [n_snap][n_tot][2] float64) and
- * img (device [n_snap][n_tot][2] int32) stack n_snap >= 2 snapshots taken at
+ * img (device [n_snap][n_tot][2] int32) stack 2 <= n_snap <= 512 snapshots at
  * a fixed stride.  For each lag lags[s] (host [n_lag], 1 .. min(32,
  * n_snap - 1), in snapshots) and drift u[t] (host [n_u][2], cells per coarse
  * step), every pair (p - lag, p) is one event on a lattice translated by
  * o dx at snapshot p - lag and by (o + u) dx at snapshot p (one coarse step
  * of a lattice moving u cells per step), o = offset[p - lag] (host
- * [n_snap][2], cells; NULL = all zero, which makes each pair the event of
- * mdlg_coarse_grain with k_prev = 0, k_cur = 1).  A homogeneous gas has the
+ * [n_snap][2], cells, |o| <= 1e6; NULL = all zero, which makes each pair
+ * the event of mdlg_coarse_grain with k_prev = 0, k_cur = 1; |u| <= 1e6).
+ * A homogeneous gas has the
  * same statistics on every translated lattice; origins that vary between
  * pairs decorrelate overlapping pairs.  Adds to counts (device int64
  * [n_rep][n_lag][n_u][50]) and, if not NULL, to moments (device float64
  * [n_rep][n_lag][5], box-frame displacement sums as in mdlg_coarse_grain,
  * the same for every drift).  n_lag <= 32, n_u <= 16, n_lag * n_u <= 256.
  * Synchronises the stream.  Counts are bitwise those of the per-pair calls;
- * moments use a fixed-order reduction. */
+ * moments use a fixed-order reduction.  EINVAL (counts unspecified) when an
+ * unwrapped cell q + lx * img leaves the 32-bit range. */
 mdlg_status mdlg_coarse_grain_series(int32_t n_rep, const int64_t* offsets, const double* box_l,
                                      const int32_t* lx, int32_t n_snap, const double* pos,
                                      const int32_t* img, int32_t n_lag, const int32_t* lags,
