@@ -93,6 +93,11 @@ typedef struct {
                                cells                                              */
     int32_t gather_batch;   /* kernel 1: neighbour loads issued per batch, 0 = 8;
                                4, 8 or 16                                         */
+    int32_t fuse_steps;     /* kernel 3: 0 = two consecutive ordinary steps per
+                               launch where possible (square tiles of cells
+                               with a one-cell halo; positions and velocities
+                               of the first step stay in LDS), 1 = one step per
+                               launch.  Results are the same either way.        */
 } lj_params;
 
 typedef struct lj_md lj_md; /* opaque handle; owns all device state */
@@ -188,6 +193,8 @@ typedef struct {
     int32_t cells_per_side; /* cell-list cells per side of replica 0            */
     int32_t block_size;
     double cell_width;      /* of replica 0                                     */
+    int32_t steps_per_launch; /* ordinary MD steps per step-kernel launch: 1 or 2 */
+    int32_t reserved;
 } lj_md_info_t;
 mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info);
 

@@ -85,11 +85,11 @@ def mdlg_velocity_table() -> np.ndarray:
 # ------------------------------------------------------------------ MD ---
 
 def lj_params(n, box_l, dt=1e-4, rc=2.5, eps=1.0, energy_shift=True, force_bits=64, skin=0.0,
-              rebuild_every=0, block_size=0, step_kernel=0, gather_batch=0) -> LJParams:
+              rebuild_every=0, block_size=0, step_kernel=0, gather_batch=0, fuse_steps=0) -> LJParams:
     return LJParams(n=int(n), box_l=float(box_l), dt=float(dt), rc=float(rc), eps=float(eps),
                     energy_shift=1 if energy_shift else 0, force_bits=int(force_bits), skin=float(skin),
                     rebuild_every=int(rebuild_every), block_size=int(block_size), step_kernel=int(step_kernel),
-                    gather_batch=int(gather_batch))
+                    gather_batch=int(gather_batch), fuse_steps=int(fuse_steps))
 
 
 def lj_md_init(params: LJParams, pos0, vel0, stream=None) -> C.c_void_p:

@@ -44,6 +44,7 @@ class LJParams(C.Structure):
         ("block_size", C.c_int32),
         ("step_kernel", C.c_int32),
         ("gather_batch", C.c_int32),
+        ("fuse_steps", C.c_int32),
     ]
 
 
@@ -61,6 +62,8 @@ class Info(C.Structure):
         ("cells_per_side", C.c_int32),
         ("block_size", C.c_int32),
         ("cell_width", C.c_double),
+        ("steps_per_launch", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

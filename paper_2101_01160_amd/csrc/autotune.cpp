@@ -123,8 +123,9 @@ void cache_store(const std::string& sig, int kernel, int block, double skin, con
     if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);
     FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;  // a cache that cannot be written is not an error
-    std::fprintf(f, "%s %d %d %.6g", sig.c_str(), kernel, block, skin);
-    for (auto& kv : cls) std::fprintf(f, " %d %.6g", kv.first, kv.second);
+    // full precision, so that a cached choice reproduces the tuned values exactly
+    std::fprintf(f, "%s %d %d %.17g", sig.c_str(), kernel, block, skin);
+    for (auto& kv : cls) std::fprintf(f, " %d %.17g", kv.first, kv.second);
     std::fprintf(f, "\n");
     std::fclose(f);
 }

@@ -53,6 +53,8 @@ struct RepDev {
     int tile0, ntile;  // slot tiles (blocks of the block size) of this replica
     int ttile0, nttile;  // cell tiles of the step kernel: nc rows x tpr tiles of tw cells
     int tw, tpr;
+    // two-step tiles: pT x pT cells, pts per side, the first global index pt0
+    int pt0, pT, pts, pnt;
     // coarse-graining lattice
     int lx, pad_;
     double inv_lat, sx, sy;  // lx / L; frame drift per coarse step (u * dx)
@@ -81,6 +83,12 @@ struct StepArgs {
     int stage_max;  // tile kernel: largest staged particle count (<= its LDS capacity)
     const short* __restrict__ nbl;          // neighbour lists [maxnb][S]: slot offsets
     const unsigned char* __restrict__ nbc;  // neighbour counts [S]
+    // two-step launches
+    double2* __restrict__ vout;                 // velocities written by the two-step kernel
+    const int* __restrict__ plist;              // [tiles][kPairCap]: owned slots, then halo slots
+    const int2* __restrict__ pcnt;              // [tiles]: (owned, staged)
+    const unsigned short* __restrict__ nbl2;    // [maxnb][S]: neighbour as index into its tile's list
+    const int* __restrict__ ptile_rep;          // [tiles] replica
     int* __restrict__ cell_acc;
     const long long* __restrict__ event_k;
     // observation
@@ -735,56 +743,27 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
     nbc[s] = (unsigned char)cnt;
 }
 
-// One velocity-Verlet step, one thread per slot, pair forces over the slot's
-// neighbour list (FIRST: the stored velocity is a full-step one; CG: this step
-// ends a coarse step).  Per neighbour: one coalesced index load, one position
-// gather, the minimum image through rint, and the pair force with the
-// reciprocal from the hardware estimate refined by Newton steps.
-template <int BS, bool F32, bool FIRST, bool CG>
-__global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
-    __shared__ int hist[MDLG_NCOUNTS];
-    __shared__ double red[BS / 64][4];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.tile_rep[tile]);
-    const RepDev& R = a.reps[r];
-    const double L = R.L, halfL = R.halfL, rc2 = R.rc2, eps24 = R.eps24;
-    const double invL = 1.0 / L;
-    const float rc2f = R.rc2f, eps24f = R.eps24f;
-    const int tid = threadIdx.x;
-    const int s = tile * BS + tid;
-    const int S = a.nslots;
-    const int nact_blk = min(BS, max(0, R.n - (tile * BS - R.slot0)));
-    const bool act = tid < nact_blk;
-    if (CG && tid < MDLG_NCOUNTS) hist[tid] = 0;
-
-    const double2 p = a.pin[s];
-    double2 v = a.vel[s];
-    const int nn = act ? a.nbc[s] : 0;
-    // A wave whose particles all lie two cell widths or more inside the box has
-    // no neighbour across the periodic edge: its separations need no image.
-    const double edge = 2.0 * R.w;
-    const bool near_edge = act && (p.x < edge || p.x > L - edge || p.y < edge || p.y > L - edge);
-    const bool interior = __ballot(near_edge) == 0ull;
+// Pair force on a particle at p from the nn entries of its neighbour list
+// (entry j at list[off + j * stride]); fetch(entry) returns the neighbour's
+// position.  Four entries per pass: four independent index loads, then four
+// position loads, then the arithmetic (entries past the list are masked).
+// Without `interior` every separation goes through the minimum image, which
+// leaves separations below L/2 unchanged bit for bit.
+template <bool F32, typename Entry, typename Fetch>
+__device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
+                                            unsigned int stride, Fetch fetch, bool interior, double L, double invL,
+                                            double rc2, double eps24, float rc2f, float eps24f, double& fx,
+                                            double& fy) {
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
-    const short* __restrict__ nbl = a.nbl;
-    const int srel = s - R.slot0, nr = R.n;
-    unsigned int off = (unsigned int)s;
-    const unsigned int stride = (unsigned int)a.nslots;
-    // four neighbours per pass: four independent index loads, then four
-    // position gathers, then the arithmetic (slots past the list are masked)
     constexpr int U = 4;
     for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
         int kk[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) kk[u] = nbl[j0 + u < nn ? off + u * stride : off];
+        for (int u = 0; u < U; ++u) kk[u] = list[j0 + u < nn ? off + u * stride : off];
         double2 q[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int kr = srel + kk[u];
-            kr = kr < 0 ? kr + nr : (kr >= nr ? kr - nr : kr);
-            q[u] = a.pin[R.slot0 + kr];
-        }
+        for (int u = 0; u < U; ++u) q[u] = fetch(kk[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool valid = j0 + u < nn;
@@ -818,25 +797,77 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
             }
         }
     }
+    fx = F32 ? (double)bx : ax;
+    fy = F32 ? (double)by : ay;
+}
+
+// Velocity-Verlet update with the force at the current position: complete
+// the half-step velocity (not on the first step, whose velocity is a full-step
+// one), kick, drift, wrap into [0, L) with the image change in (wx, wy).
+template <bool FIRST>
+__device__ __forceinline__ double2 vv_update(double2 p, double2& v, double fx, double fy, double dt, double hdt,
+                                             double L, int& wx, int& wy) {
+    if (!FIRST) {
+        v.x = v.x + hdt * fx;
+        v.y = v.y + hdt * fy;
+    }
+    v.x = v.x + hdt * fx;
+    v.y = v.y + hdt * fy;
+    double2 pn;
+    pn.x = p.x + dt * v.x;
+    pn.y = p.y + dt * v.y;
+    wx = 0;
+    wy = 0;
+    if (pn.x >= L) { pn.x -= L; wx = 1; }
+    else if (pn.x < 0.0) { pn.x += L; wx = -1; if (pn.x >= L) { pn.x = 0.0; wx = 0; } }
+    if (pn.y >= L) { pn.y -= L; wy = 1; }
+    else if (pn.y < 0.0) { pn.y += L; wy = -1; if (pn.y >= L) { pn.y = 0.0; wy = 0; } }
+    return pn;
+}
+
+// One velocity-Verlet step, one thread per slot, pair forces over the slot's
+// neighbour list (FIRST: the stored velocity is a full-step one; CG: this step
+// ends a coarse step).  Per neighbour: one coalesced index load, one position
+// gather, the minimum image through rint, and the pair force with the
+// reciprocal from the hardware estimate refined by Newton steps.
+template <int BS, bool F32, bool FIRST, bool CG>
+__global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
+    __shared__ int hist[MDLG_NCOUNTS];
+    __shared__ double red[BS / 64][4];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.tile_rep[tile]);
+    const RepDev& R = a.reps[r];
+    const double L = R.L, halfL = R.halfL;
+    const double invL = 1.0 / L;
+    const int tid = threadIdx.x;
+    const int s = tile * BS + tid;
+    const int nact_blk = min(BS, max(0, R.n - (tile * BS - R.slot0)));
+    const bool act = tid < nact_blk;
+    if (CG && tid < MDLG_NCOUNTS) hist[tid] = 0;
+
+    const double2 p = a.pin[s];
+    double2 v = a.vel[s];
+    const int nn = act ? a.nbc[s] : 0;
+    // A wave whose particles all lie two cell widths or more inside the box has
+    // no neighbour across the periodic edge: its separations need no image.
+    const double edge = 2.0 * R.w;
+    const bool near_edge = act && (p.x < edge || p.x > L - edge || p.y < edge || p.y > L - edge);
+    const bool interior = __ballot(near_edge) == 0ull;
+    const int srel = s - R.slot0, nr = R.n, slot0 = R.slot0;
+    const double2* __restrict__ pin = a.pin;
+    auto fetch = [&](int k) {
+        int kr = srel + k;
+        kr = kr < 0 ? kr + nr : (kr >= nr ? kr - nr : kr);
+        return pin[slot0 + kr];
+    };
+    double fx, fy;
+    nlist_force<F32>(p, nn, a.nbl, (unsigned int)s, (unsigned int)a.nslots, fetch, interior, L, invL, R.rc2, R.eps24,
+                     R.rc2f, R.eps24f, fx, fy);
     int idx = MDLG_NQ;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (act) {
-        const double fx = F32 ? (double)bx : ax;
-        const double fy = F32 ? (double)by : ay;
-        if (!FIRST) {
-            v.x = v.x + a.hdt * fx;
-            v.y = v.y + a.hdt * fy;
-        }
-        v.x = v.x + a.hdt * fx;
-        v.y = v.y + a.hdt * fy;
-        double2 pn;
-        pn.x = p.x + a.dt * v.x;
-        pn.y = p.y + a.dt * v.y;
-        int wx = 0, wy = 0;
-        if (pn.x >= L) { pn.x -= L; wx = 1; }
-        else if (pn.x < 0.0) { pn.x += L; wx = -1; if (pn.x >= L) { pn.x = 0.0; wx = 0; } }
-        if (pn.y >= L) { pn.y -= L; wy = 1; }
-        else if (pn.y < 0.0) { pn.y += L; wy = -1; if (pn.y >= L) { pn.y = 0.0; wy = 0; } }
+        int wx, wy;
+        const double2 pn = vv_update<FIRST>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
         if (wx | wy) {
             int2 im = a.img[s];
             im.x += wx;
@@ -884,6 +915,228 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
             a.mpart[(long long)tile * MDLG_NMOMENTS + 1 + tid] = sum;
         }
         if (tid == 0) a.mpart[(long long)tile * MDLG_NMOMENTS] = 2.0 * (double)nact_blk;
+    }
+}
+
+// Two consecutive ordinary steps per launch.  The box is cut into square tiles
+// of pT x pT cells; a block owns the particles of one tile.  Its staged set is
+// those particles followed by the particles of the one-cell ring around the
+// tile, which holds every neighbour of an owned particle (neighbour lists
+// reach one cell width).  First step: every staged particle is advanced, its
+// neighbours read from global memory at time t, and the new positions kept in
+// LDS (halo particles are advanced by their own tiles too: the work is
+// repeated, not shared).  Second step: owned particles only, with neighbours
+// read from LDS through lists of staged indices built at the rebuild.  Both
+// steps run the same force and update code as the one-step kernel, in the
+// same neighbour order, so the result equals two one-step launches bit for
+// bit.  Velocities go to a second buffer: other tiles still read the old ones.
+constexpr int kPairCap = 768;   // staged particles of one tile, owned + halo
+constexpr int kStep2BS = 512;   // threads of the two-step kernel
+constexpr int kPairSeg = 104;   // row segments of one tile: 3 pT + 6 <= 102
+
+// Per tile, after the neighbour lists: the staged slots (owned rows, then the
+// two halo rows and the two halo columns, each as contiguous slot ranges of
+// the row-major cell order) and the owned particles' neighbour lists as
+// staged indices.  A tile that stages more than kPairCap particles, or a
+// neighbour outside the staged set, raises ERR_NLIST.
+__global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
+                                                    const int* __restrict__ ptrep, const short* __restrict__ nbl,
+                                                    const unsigned char* __restrict__ nbc, int S, int* __restrict__ plist,
+                                                    int2* __restrict__ pcnt, unsigned short* __restrict__ nbl2,
+                                                    int* err) {
+    __shared__ int sa[kPairSeg], sn[kPairSeg], so[kPairSeg + 1];
+    const int t = blockIdx.x;
+    const RepDev& R = reps[ptrep[t]];
+    const int nc = R.nc, T = R.pT;
+    const int lt = t - R.pt0, ty = lt / R.pts, tx = lt % R.pts;
+    const int c0 = tx * T, c1 = min(c0 + T, nc), r0 = ty * T, r1 = min(r0 + T, nc);
+    const int nr = r1 - r0;
+    const int cl = c0 - 1 < 0 ? nc - 1 : c0 - 1;  // left halo column
+    const int cr = c1 >= nc ? 0 : c1;             // right halo column
+    const bool inner = c0 >= 1 && c1 <= nc - 1;    // halo rows as one range c0 - 1 .. c1
+    const int hs = inner ? 1 : 3;
+    const int ns = nr + 2 * hs + 2 * nr;
+    // segment q: owned rows, then the two halo rows, then the halo cells left
+    // and right of every owned row; each a range of cells ca .. cb - 1 of a row
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+        int row, ca, cb;
+        if (q < nr) {
+            row = r0 + q;
+            ca = c0;
+            cb = c1;
+        } else if (q < nr + 2 * hs) {
+            const int h = (q - nr) / hs, k = (q - nr) % hs;
+            row = h == 0 ? r0 - 1 : r1;
+            row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
+            if (inner) {
+                ca = c0 - 1;
+                cb = c1 + 1;
+            } else {
+                ca = k == 0 ? c0 : (k == 1 ? cl : cr);
+                cb = k == 0 ? c1 : ca + 1;
+            }
+        } else {
+            const int k = q - nr - 2 * hs;
+            row = r0 + k / 2;
+            ca = (k & 1) ? cr : cl;
+            cb = ca + 1;
+        }
+        const int base = R.cell0 + row * nc;
+        sa[q] = cs[base + ca];
+        sn[q] = cs[base + cb] - sa[q];
+    }
+    for (int q = ns + threadIdx.x; q < kPairSeg; q += blockDim.x) sn[q] = 0;
+    __syncthreads();
+    // exclusive prefix of the segment lengths (Hillis-Steele over 128 entries)
+    __shared__ int scan[2][128];
+    for (int q = threadIdx.x; q < 128; q += blockDim.x) scan[0][q] = q < ns ? sn[q] : 0;
+    __syncthreads();
+    int cur = 0;
+    for (int d = 1; d < 128; d *= 2) {
+        for (int q = threadIdx.x; q < 128; q += blockDim.x)
+            scan[cur ^ 1][q] = scan[cur][q] + (q >= d ? scan[cur][q - d] : 0);
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int q = threadIdx.x; q <= ns; q += blockDim.x) so[q] = q == 0 ? 0 : scan[cur][q - 1];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = so[ns];
+        if (tot > kPairCap) {
+            atomicOr(err, ERR_NLIST);
+            tot = kPairCap;
+        }
+        pcnt[t] = make_int2(min(so[nr], kPairCap), tot);
+    }
+    // non-empty segments sorted by first slot, for the staged index of a slot
+    __shared__ int ss[kPairSeg], se[kPairSeg], sl[kPairSeg];
+    __shared__ int nne;
+    if (threadIdx.x == 0) nne = 0;
+    __syncthreads();
+    for (int g = threadIdx.x; g < ns; g += blockDim.x) {
+        if (sn[g] == 0) continue;
+        int rank = 0;
+        for (int h = 0; h < ns; ++h) rank += (sn[h] > 0 && sa[h] < sa[g]) ? 1 : 0;
+        ss[rank] = sa[g];
+        se[rank] = sa[g] + sn[g];
+        sl[rank] = so[g];
+        atomicAdd(&nne, 1);
+    }
+    __syncthreads();
+    const int tot = min(so[ns], kPairCap), own = min(so[nr], kPairCap), ne = nne;
+    int* list = plist + (long long)t * kPairCap;
+    // segment of staged index q: the last g < nseg with so[g] <= q
+    auto seg_of = [&](int q, int nseg) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (so[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+        const int g = seg_of(q, ns);
+        list[q] = sa[g] + (q - so[g]);
+    }
+    // owned particles' neighbour lists as staged indices
+    const int slot0 = R.slot0, nrep = R.n;
+    for (int q = threadIdx.x; q < own; q += blockDim.x) {
+        {
+            const int g = seg_of(q, nr);
+            const int s = sa[g] + (q - so[g]);
+            const int nn = nbc[s];
+            for (int j = 0; j < nn; ++j) {
+                int kr = (s - slot0) + nbl[(long long)j * S + s];
+                kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
+                const int k = slot0 + kr;
+                // last sorted segment starting at or before k
+                int lo = 0, hi = ne - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (ss[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                int loc = -1;
+                if (ne > 0 && ss[lo] <= k && k < se[lo]) loc = sl[lo] + (k - ss[lo]);
+                if (loc < 0 || loc >= tot) {
+                    atomicOr(err, ERR_NLIST);
+                    loc = 0;
+                }
+                nbl2[(long long)j * S + s] = (unsigned short)loc;
+            }
+        }
+    }
+}
+
+template <int BS, bool F32>
+__global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
+    __shared__ double2 xs[kPairCap];
+    __shared__ double2 vs[kPairCap];
+    __shared__ char2 wr[kPairCap];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
+    const RepDev& R = a.reps[r];
+    const double L = R.L;
+    const double invL = 1.0 / L;
+    const int2 c = a.pcnt[t];
+    const int own = c.x, tot = c.y;
+    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
+    // A tile two cells or more from every box edge stages particles, and has
+    // neighbours of them, only within the box: separations need no image.
+    const int nc = R.nc, T = R.pT, lt = t - R.pt0;
+    const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
+    const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
+    const bool interior = c0 >= 2 && r0 >= 2 && c1 <= nc - 2 && r1 <= nc - 2;
+    const double2* __restrict__ pin = a.pin;
+    const int nr = R.n, slot0 = R.slot0;
+    const unsigned int S = (unsigned int)a.nslots;
+    for (int q = threadIdx.x; q < tot; q += BS) {
+        const int s = list[q];
+        const double2 p = pin[s];
+        double2 v = a.vel[s];
+        const int nn = a.nbc[s];
+        const int srel = s - slot0;
+        auto fetch = [&](int k) {
+            int kr = srel + k;
+            kr = kr < 0 ? kr + nr : (kr >= nr ? kr - nr : kr);
+            return pin[slot0 + kr];
+        };
+        double fx, fy;
+        nlist_force<F32>(p, nn, a.nbl, (unsigned int)s, S, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
+                         R.eps24f, fx, fy);
+        int wx, wy;
+        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        xs[q] = pn;
+        if (q < own) {
+            vs[q] = v;
+            wr[q] = make_char2((signed char)wx, (signed char)wy);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < own; q += BS) {
+        const int s = list[q];
+        const double2 p = xs[q];
+        double2 v = vs[q];
+        const int nn = a.nbc[s];
+        auto fetch = [&](int k) { return xs[k]; };
+        double fx, fy;
+        nlist_force<F32>(p, nn, a.nbl2, (unsigned int)s, S, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
+                         R.eps24f, fx, fy);
+        int wx, wy;
+        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        const char2 w1 = wr[q];
+        wx += w1.x;
+        wy += w1.y;
+        if (wx | wy) {
+            int2 im = a.img[s];
+            im.x += wx;
+            im.y += wy;
+            a.img[s] = im;
+        }
+        if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
+        a.pout[s] = pn;
+        a.vout[s] = v;
     }
 }
 
@@ -1249,15 +1502,15 @@ struct RepHost {
 };
 
 struct GraphKey {
-    int K, phase, ppar, opar;
+    int K, phase, ppar, opar, vpar;
     bool operator<(const GraphKey& o) const {
-        return std::tie(K, phase, ppar, opar) < std::tie(o.K, o.phase, o.ppar, o.opar);
+        return std::tie(K, phase, ppar, opar, vpar) < std::tie(o.K, o.phase, o.ppar, o.opar, o.vpar);
     }
 };
 
 struct GraphVal {
     hipGraphExec_t exec;
-    int ppar_after, opar_after;
+    int ppar_after, opar_after, vpar_after;
     int events;
 };
 
@@ -1288,6 +1541,13 @@ struct lj_md {
     int* d_tinfo = nullptr;
     short* nbl = nullptr;     // neighbour lists (step kernel 3)
     unsigned char* nbc = nullptr;
+    // two ordinary steps per launch (step kernel 3)
+    bool two_step = false;
+    int npt = 0;                      // two-step tiles
+    int* d_ptrep = nullptr;           // [npt] replica
+    int* plist = nullptr;             // [npt][kPairCap]
+    int2* pcnt = nullptr;             // [npt]
+    unsigned short* nbl2 = nullptr;   // [maxnb][S]
     double2* pref = nullptr;  // positions at the list build
     int maxnb = 0;
     int* d_hpart = nullptr;
@@ -1300,7 +1560,7 @@ struct lj_md {
     int *key = nullptr, *rank = nullptr, *perm = nullptr, *permid = nullptr, *cellof = nullptr;
     int *cnt = nullptr, *cs = nullptr, *bsum = nullptr;
     int nscan = 0;
-    int ppar = 0, opar = 0;  // current buffer of pos / of the other per-particle arrays
+    int ppar = 0, opar = 0, vpar = 0;  // current buffer of pos / of img, id, snap / of vel
     bool vel_full = true;
     bool have_cellof = false;
     bool broken = false;
@@ -1329,8 +1589,9 @@ struct lj_md {
     struct TimedGraphs {
         std::array<hipGraphExec_t, 3> g;
         int M, tail_events;
+        int ppar_after, opar_after, vpar_after;
     };
-    std::map<std::tuple<int, int, int, int>, TimedGraphs> tgraphs;
+    std::map<std::tuple<int, int, int, int, int>, TimedGraphs> tgraphs;
     bool use_graphs = true;
 };
 
@@ -1367,7 +1628,8 @@ StepArgs make_args(lj_md* md) {
     StepArgs a{};
     a.pin = md->pos[md->ppar];
     a.pout = md->pos[md->ppar ^ 1];
-    a.vel = md->vel[md->opar];
+    a.vel = md->vel[md->vpar];
+    a.vout = md->vel[md->vpar ^ 1];
     a.img = md->img[md->opar];
     a.cs = md->cs;
     a.reps = md->d_reps;
@@ -1386,6 +1648,10 @@ StepArgs make_args(lj_md* md) {
     a.stage_max = md->stage_max;
     a.nbl = md->nbl;
     a.nbc = md->nbc;
+    a.plist = md->plist;
+    a.pcnt = md->pcnt;
+    a.nbl2 = md->nbl2;
+    a.ptile_rep = md->d_ptrep;
     a.cell_acc = md->cell_acc;
     a.event_k = md->d_event_k;
     a.id = md->id[md->opar];
@@ -1448,6 +1714,35 @@ hipError_t launch_step(lj_md* md, hipStream_t st, bool first, bool cg, hipEvent_
     return e;
 }
 
+// Two ordinary steps in one launch (see k_step2_nlist).
+hipError_t launch_step2(lj_md* md, hipStream_t st) {
+    StepArgs a = make_args(md);
+    const int grid = md->npt;
+    if (md->f32)
+        hipLaunchKernelGGL((k_step2_nlist<kStep2BS, true>), dim3(grid), dim3(kStep2BS), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_step2_nlist<kStep2BS, false>), dim3(grid), dim3(kStep2BS), 0, st, a);
+    md->ppar ^= 1;
+    md->vpar ^= 1;
+    return hipGetLastError();
+}
+
+// `count` ordinary steps (no coarse-graining event), two per launch where the
+// handle allows it.
+hipError_t launch_plain_steps(lj_md* md, hipStream_t st, int count) {
+    hipError_t e = hipSuccess;
+    while (count > 0 && e == hipSuccess) {
+        if (md->two_step && count >= 2) {
+            e = launch_step2(md, st);
+            count -= 2;
+        } else {
+            e = launch_step(md, st, false, false);
+            count -= 1;
+        }
+    }
+    return e;
+}
+
 hipError_t launch_observe(lj_md* md, hipStream_t st, double2* opos, double2* ovel, int2* oimg, double2* ofrc,
                           bool energy) {
     StepArgs a = make_args(md);
@@ -1494,8 +1789,8 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     Bufs b;
     b.pos_o = md->pos[md->ppar];
     b.pos_n = md->pos[md->ppar ^ 1];
-    b.vel_o = md->vel[o];
-    b.vel_n = md->vel[o ^ 1];
+    b.vel_o = md->vel[md->vpar];
+    b.vel_n = md->vel[md->vpar ^ 1];
     b.img_o = md->img[o];
     b.img_n = md->img[o ^ 1];
     b.id_o = md->id[o];
@@ -1508,8 +1803,13 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
         hipLaunchKernelGGL(k_nlist_build, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
                            (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
                            md->maxnb, md->nbl, md->nbc, md->pref, md->d_err);
+    if (md->two_step)
+        hipLaunchKernelGGL(k_pair_build, dim3(md->npt), dim3(256), 0, st, (const int*)md->cs,
+                           (const RepDev*)md->d_reps, (const int*)md->d_ptrep, (const short*)md->nbl,
+                           (const unsigned char*)md->nbc, S, md->plist, md->pcnt, md->nbl2, md->d_err);
     md->ppar ^= 1;
     md->opar ^= 1;
+    md->vpar ^= 1;
     md->have_cellof = true;
     md->since_rebuild = 0;
     return hipGetLastError();
@@ -1539,20 +1839,23 @@ hipError_t eager_step(lj_md* md, hipStream_t st) {
 
 // rebuild + K steps, replayed from a captured graph.
 mdlg_status graph_unit(lj_md* md, hipStream_t st) {
-    GraphKey key{md->K, md->cg_on ? (int)(md->cg_t % md->s_cg) : -1, md->ppar, md->opar};
+    GraphKey key{md->K, md->cg_on ? (int)(md->cg_t % md->s_cg) : -1, md->ppar, md->opar, md->vpar};
     auto it = md->graphs.find(key);
     if (it == md->graphs.end()) {
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
         MDLG_HIP(hipStreamBeginCapture(md->cap, hipStreamCaptureModeThreadLocal));
         hipError_t e = launch_rebuild(md, md->cap);
-        for (int j = 0; j < md->K && e == hipSuccess; ++j) {
+        for (int j = 0; j < md->K && e == hipSuccess;) {
             const bool ev = event_due(md, md->cg_t + 1);
-            e = launch_step(md, md->cap, false, ev);
-            md->since_rebuild += 1;
+            const bool pair = md->two_step && !ev && j + 1 < md->K && !event_due(md, md->cg_t + 2);
+            const int n = pair ? 2 : 1;
+            e = pair ? launch_step2(md, md->cap) : launch_step(md, md->cap, false, ev);
+            md->since_rebuild += n;
             if (md->cg_on) {
-                md->cg_t += 1;
+                md->cg_t += n;
                 if (ev) md->events += 1;
             }
+            j += n;
         }
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(md->cap, &g);
@@ -1561,11 +1864,12 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
         hipGraphExec_t ex = nullptr;
         MDLG_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
-        GraphVal val{ex, md->ppar, md->opar, (int)(md->events - ev0)};
+        GraphVal val{ex, md->ppar, md->opar, md->vpar, (int)(md->events - ev0)};
         md->graphs[key] = val;
         // the capture only recorded work: restore the counters, then replay
         md->ppar = key.ppar;
         md->opar = key.opar;
+        md->vpar = key.vpar;
         md->steps_done = steps0;
         md->cg_t = cg_t0;
         md->events = ev0;
@@ -1574,6 +1878,7 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
     MDLG_HIP(hipGraphLaunch(it->second.exec, st));
     md->ppar = it->second.ppar_after;
     md->opar = it->second.opar_after;
+    md->vpar = it->second.vpar_after;
     md->steps_done += md->K;
     md->since_rebuild = md->K;
     md->have_cellof = true;
@@ -1602,6 +1907,7 @@ mdlg_status check_params(const lj_params& p, int r) {
     if (p.step_kernel < 0 || p.step_kernel > 3) return bad("step_kernel must be 0, 1, 2 or 3");
     if (p.gather_batch != 0 && p.gather_batch != 4 && p.gather_batch != 8 && p.gather_batch != 16)
         return bad("gather_batch must be 0, 4, 8 or 16");
+    if (p.fuse_steps != 0 && p.fuse_steps != 1) return bad("fuse_steps must be 0 or 1");
     return MDLG_OK;
 }
 
@@ -1716,6 +2022,30 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     }
     md->TT = (int)ttiles;
     md->nscan = (md->C + kScanTile - 1) / kScanTile;
+    // two-step tiles: about 460 staged particles on average, so that one
+    // block of kStep2BS threads advances a tile in one pass per step; a ring
+    // of distinct cells needs nc >= pT + 2
+    md->two_step = md->variant == 3 && p[0].fuse_steps == 0;
+    {
+        long long pt = 0;
+        for (int r = 0; r < n_rep && md->two_step; ++r) {
+            RepDev& d = md->reps[r].d;
+            const double ppc = std::max((double)d.n / ((double)d.nc * d.nc), 1e-9);
+            int T = (int)std::floor(std::sqrt(460.0 / ppc)) - 2;
+            T = std::min(std::min(T, 32), d.nc - 2);
+            if (T < 2) {
+                md->two_step = false;
+                break;
+            }
+            d.pT = T;
+            d.pts = (d.nc + T - 1) / T;
+            d.pnt = d.pts * d.pts;
+            d.pt0 = (int)pt;
+            pt += d.pnt;
+        }
+        if (pt >= (1LL << 31) / kPairCap) md->two_step = false;
+        md->npt = md->two_step ? (int)pt : 0;
+    }
 
     auto A = [&](hipError_t e) { return e == hipSuccess; };
     bool ok = A(dalloc(&md->d_reps, n_rep)) && A(dalloc(&md->d_tile_rep, md->ntile)) &&
@@ -1751,17 +2081,22 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             return destroy_on_fail(md, fail(MDLG_EINVAL, "lj_md_init: neighbour lists of this size exceed 2^30 "
                                                          "entries; use step_kernel 1"));
         ok = A(dalloc(&md->nbl, (size_t)md->maxnb * md->S)) && A(dalloc(&md->nbc, md->S)) && A(dalloc(&md->pref, md->S));
+        if (ok && md->two_step)
+            ok = A(dalloc(&md->d_ptrep, md->npt)) && A(dalloc(&md->plist, (size_t)md->npt * kPairCap)) &&
+                 A(dalloc(&md->pcnt, md->npt)) && A(dalloc(&md->nbl2, (size_t)md->maxnb * md->S));
     }
     if (!ok) return destroy_on_fail(md, fail(MDLG_ENOMEM, "lj_md_init: device allocation failed"));
 
     std::vector<RepDev> hd(n_rep);
-    std::vector<int> trep(md->ntile), ttrep(md->TT);
+    std::vector<int> trep(md->ntile), ttrep(md->TT), ptrep(md->npt);
     std::vector<long long> hpoff(n_rep);
     for (int r = 0; r < n_rep; ++r) {
         hd[r] = md->reps[r].d;
         hpoff[r] = md->reps[r].poff;
         for (int t = 0; t < hd[r].ntile; ++t) trep[hd[r].tile0 + t] = r;
         for (int t = 0; t < hd[r].nttile; ++t) ttrep[hd[r].ttile0 + t] = r;
+        if (md->two_step)
+            for (int t = 0; t < hd[r].pnt; ++t) ptrep[hd[r].pt0 + t] = r;
     }
     long long* d_poff = nullptr;
     if (hipMalloc((void**)&d_poff, sizeof(long long) * n_rep) != hipSuccess)
@@ -1770,6 +2105,8 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     if (e == hipSuccess) e = hipMemcpy(md->d_tile_rep, trep.data(), sizeof(int) * md->ntile, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_poff, hpoff.data(), sizeof(long long) * n_rep, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(md->d_ttile_rep, ttrep.data(), sizeof(int) * md->TT, hipMemcpyHostToDevice);
+    if (e == hipSuccess && md->two_step)
+        e = hipMemcpy(md->d_ptrep, ptrep.data(), sizeof(int) * md->npt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_done, 0, sizeof(unsigned int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_err, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->cnt, 0, sizeof(int) * md->C, st);
@@ -1944,10 +2281,10 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     mdlg_status status = MDLG_OK;
     for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
         const int phase = md->cg_on ? (int)(md->cg_t % md->s_cg) : -1;
-        const auto key = std::make_tuple(K, md->ppar, md->opar, phase);
+        const auto key = std::make_tuple(K, md->ppar, md->opar, md->vpar, phase);
         auto it = cache.find(key);
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
-        Graphs G{{nullptr, nullptr, nullptr}, K, 0};
+        Graphs G{{nullptr, nullptr, nullptr}, K, 0, 0, 0, 0};
         if (it == cache.end()) {
             // ordinary steps at the start of the unit, before its first coarse-graining step
             if (md->cg_on) {
@@ -1958,27 +2295,30 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
             status = capture(md, [&](hipStream_t cs) { return launch_rebuild(md, cs); }, &G.g[0]);
             if (status == MDLG_OK)
                 status = capture(md, [&](hipStream_t cs) {
-                    hipError_t e = hipSuccess;
-                    for (int j = 0; j < M && e == hipSuccess; ++j) {
-                        e = launch_step(md, cs, false, false);
-                        md->cg_t += md->cg_on ? 1 : 0;
-                    }
+                    hipError_t e = launch_plain_steps(md, cs, M);
+                    md->cg_t += md->cg_on ? M : 0;
                     return e;
                 }, &G.g[1]);
             if (status == MDLG_OK)
                 status = capture(md, [&](hipStream_t cs) {
                     hipError_t e = hipSuccess;
-                    for (int j = M; j < K && e == hipSuccess; ++j) {
+                    for (int j = M; j < K && e == hipSuccess;) {
                         const bool ev = event_due(md, md->cg_t + 1);
-                        e = launch_step(md, cs, false, ev);
+                        const bool pair = md->two_step && !ev && j + 1 < K && !event_due(md, md->cg_t + 2);
+                        const int n = pair ? 2 : 1;
+                        e = pair ? launch_step2(md, cs) : launch_step(md, cs, false, ev);
                         if (md->cg_on) {
-                            md->cg_t += 1;
+                            md->cg_t += n;
                             if (ev) md->events += 1;
                         }
+                        j += n;
                     }
                     return e;
                 }, &G.g[2]);
             G.tail_events = (int)(md->events - ev0);
+            G.ppar_after = md->ppar;
+            G.opar_after = md->opar;
+            G.vpar_after = md->vpar;
             if (status != MDLG_OK) {
                 for (auto x : G.g)
                     if (x) (void)hipGraphExecDestroy(x);
@@ -1989,6 +2329,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
             // captures only recorded work: restore the step counters
             md->ppar = std::get<1>(key);
             md->opar = std::get<2>(key);
+            md->vpar = std::get<3>(key);
             md->steps_done = steps0;
             md->cg_t = cg_t0;
             md->events = ev0;
@@ -2017,8 +2358,9 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
         }
         order.push_back(rec);
         // host state after the unit: the capture's effect, replayed
-        md->ppar = md->ppar ^ 1 ^ (K & 1);
-        md->opar = md->opar ^ 1;
+        md->ppar = G.ppar_after;
+        md->opar = G.opar_after;
+        md->vpar = G.vpar_after;
         md->steps_done += K;
         md->since_rebuild = K;
         md->have_cellof = true;
@@ -2110,6 +2452,8 @@ extern "C" mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info) {
     info->cells_per_side = md->reps[0].d.nc;
     info->block_size = md->BS;
     info->cell_width = md->reps[0].d.w;
+    info->steps_per_launch = md->two_step ? 2 : 1;
+    info->reserved = 0;
     return MDLG_OK;
 }
 
@@ -2120,7 +2464,7 @@ extern "C" void lj_md_destroy(lj_md* md) {
     void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->d_done, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
                     md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm, md->permid,
                     md->cellof, md->cnt, md->cs, md->bsum, md->d_err, md->d_epart, md->d_eout, md->d_vmax,
-                    md->d_mpart, md->d_event_k};
+                    md->d_mpart, md->d_event_k, md->d_ptrep, md->plist, md->pcnt, md->nbl2};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete md;

@@ -330,3 +330,52 @@ def test_autotuner_returns_runnable_params(tmp_path, monkeypatch):
         off += n
     batch.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,phi,kT,kw", [
+    (512, 0.0784, 20.0, {}),
+    (2000, 0.4, 20.0, {"block_size": 128}),
+    (700, 0.4, 20.0, {"skin": 0.2, "rebuild_every": 3}),
+    (3000, 0.2, 1.0, {"force_bits": 32}),
+    (20000, 0.0784, 20.0, {"block_size": 512}),
+])
+def test_two_steps_per_launch_equal_one(n, phi, kT, kw):
+    """Two ordinary steps per launch (tiles with a staged halo) give the same
+    state, bit for bit, as one step per launch, with and without the fused
+    coarse-graining."""
+    print(f"two-step n={n} phi={phi} kT={kT} {kw}", flush=True)
+    pos0, vel0, L = mi.initial_state(n, phi, kT, 5)
+    out = []
+    for fuse in (0, 1):
+        sysm = gpu_system(pos0, vel0, L, fuse_steps=fuse, **kw)
+        assert sysm.info()["steps_per_launch"] == (2 if fuse == 0 else 1)
+        acc = sysm.attach_cg(max(7, int(L / 2.0)), 10)
+        sysm.step(13)
+        sysm.step(131)
+        pos, vel, img = (_np(t) for t in sysm.state())
+        out.append((pos, vel, img, _np(acc.counts), _np(acc.moments)))
+        sysm.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+
+
+def test_two_step_batched_replicas_equal_single():
+    import paper_2101_01160_amd as m
+    specs = [(4096, 0.0784, 20.0), (1500, 0.4, 1.0), (9000, 0.2, 5.0)]
+    states = [mi.initial_state(n, phi, kT, 11 + i) for i, (n, phi, kT) in enumerate(specs)]
+    pos = np.concatenate([s[0] for s in states])
+    vel = np.concatenate([s[1] for s in states])
+    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10) for s in states]
+    batch = m.LJSystem(_cuda(pos), _cuda(vel), params=params)
+    assert batch.info()["steps_per_launch"] == 2
+    batch.step(55)
+    bpos = _np(batch.state()[0])
+    batch.close()
+    off = 0
+    for s, p in zip(states, params):
+        single = m.LJSystem(_cuda(s[0]), _cuda(s[1]), params=[m.lj_params(p.n, p.box_l, rebuild_every=10,
+                                                                           fuse_steps=1)])
+        single.step(55)
+        assert np.array_equal(_np(single.state()[0]), bpos[off:off + p.n])
+        off += p.n
+        single.close()
