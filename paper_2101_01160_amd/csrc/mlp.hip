@@ -27,9 +27,9 @@ constexpr int kMaxSplit = 32;
 __constant__ float c_scale[kIn] = {2.5f, 0.05f, 100.0f, 5.0f, 1.0f, 1.0f};
 
 // Epilogues: STORE C; BIAS_SILU C = z = acc + bias and H = silu(z); BIAS C =
-// acc + bias; SILU_H only H = silu(acc + bias) (inference); SILU_BWD
-// H = acc * silu'(Z) (the backward pass through an activation).
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_SILU_H = 3, EPI_SILU_BWD = 4 };
+// acc + bias; SILU_BWD H = acc * silu'(Z) (the backward pass through an
+// activation).
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_SILU_BWD = 4 };
 // Operand staging modes: 0 element-wise (any strides), 1 contiguous along k,
 // 2 contiguous along the row (A: m, B: n) -- 1 and 2 load 16-byte vectors.
 enum { OP_ANY = 0, OP_K = 1, OP_ROW = 2 };
@@ -43,7 +43,7 @@ struct GemmArgs {
     const float* bias;
     float* C;  // C[m * ldc + n] (+ blockIdx.z * split_stride for split-K partials)
     long ldc;
-    bf16* H;  // bf16 output (EPI_BIAS_SILU, EPI_SILU_H, EPI_SILU_BWD)
+    bf16* H;  // bf16 output (EPI_BIAS_SILU, EPI_SILU_BWD)
     long ldh;
     const float* Z;  // pre-activations read by EPI_SILU_BWD, leading dimension ldh
     int ones_row;  // row m of A reads as all ones (bias gradient row), -1: none
@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                     continue;
                 }
                 if (EPI != EPI_STORE) z += g.bias[n];
-                if (EPI != EPI_SILU_H) C[m * g.ldc + n] = z;
-                if (EPI == EPI_BIAS_SILU || EPI == EPI_SILU_H) g.H[m * g.ldh + n] = (bf16)(z / (1.0f + __expf(-z)));
+                C[m * g.ldc + n] = z;
+                if (EPI == EPI_BIAS_SILU) g.H[m * g.ldh + n] = (bf16)(z / (1.0f + __expf(-z)));
             }
 }
 
@@ -289,6 +289,160 @@ __global__ void k_to_bf16(const float* __restrict__ w, long n, bf16* __restrict_
     if (t >= 0) wt[t] = (bf16)w[i];
 }
 
+// Whole-network inference for 64 samples per block.  The activations stay
+// in LDS from layer to layer; the weights come from the transposed bf16 copy
+// (k contiguous per output), from L2, straight into MFMA operand registers.
+// Wave w computes output columns 64 w .. 64 w + 63 of a hidden layer (4 x 4
+// tiles of 16 x 16, accumulators in registers), then every wave's results
+// replace the layer input in LDS; the last layer (49 outputs, padded to 64)
+// gives wave w the 16 rows 16 w .. 16 w + 15, whose softmax is reduced across
+// the 16 lanes that hold a row.  Same roundings as the layer-wise products:
+// scaled inputs, weights and hidden activations in bf16, fp32 accumulation,
+// fp32 biases.
+constexpr int kFB = 64;            // samples per block
+constexpr int kHLD = kHid + 8;     // LDS row stride of the activations (bf16)
+
+__device__ __forceinline__ void hidden_epilogue(const f32x4 (&acc)[4][4], const float* __restrict__ bias,
+                                                bf16 (*H)[kHLD], int wv, int lane) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = 64 * wv + 16 * j + (lane & 15);
+        const float bj = bias[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float z = acc[i][j][r] + bj;
+                H[16 * i + 4 * (lane >> 4) + r][col] = (bf16)(z / (1.0f + __expf(-z)));
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x, int B, const bf16* __restrict__ wt,
+                                                   const float* __restrict__ w, float* __restrict__ g) {
+    __shared__ __attribute__((aligned(16))) bf16 H[kFB][kHLD];
+    __shared__ __attribute__((aligned(16))) bf16 X[kFB][40];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int row0 = blockIdx.x * kFB;
+    for (int i = tid; i < kFB * 32; i += 256) {
+        const int r = i >> 5, k = i & 31;
+        float v = 0.f;
+        if (k < kIn && row0 + r < B) v = x[(long)(row0 + r) * kIn + k] * c_scale[k];
+        X[r][k] = (bf16)v;
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    const bf16 zero = (bf16)0.0f;
+    f32x4 acc[4][4];
+    // layer 1: k = 6, one MFMA step over k padded to 32
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    {
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&X[16 * i + lr][lk]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = 64 * wv + 16 * j + lr;
+            bf16x8 b;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[e] = lk + e < kIn ? wt[kW1 + col * kIn + lk + e] : zero;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
+        }
+    }
+    hidden_epilogue(acc, w + kB1, H, wv, lane);
+    __syncthreads();
+    // layers 2 and 3: k = 256
+    const long wo[2] = {kW2, kW3}, bo[2] = {kB2, kB3};
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const bf16* __restrict__ W = wt + wo[l] + (64 * wv + lr) * kHid + lk;
+        // the weight fragments of the next k step are in flight during this one's products
+        bf16x8 b[4], bn[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kHid);
+#pragma unroll 1
+        for (int ks = 0; ks < kHid / 32; ++ks) {
+            if (ks + 1 < kHid / 32) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bn[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kHid + 32 * (ks + 1));
+            }
+            bf16x8 a[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&H[16 * i + lr][32 * ks + lk]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (ks + 1 < kHid / 32) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = bn[j];
+            }
+        }
+        __syncthreads();  // every wave has read this layer's input
+        hidden_epilogue(acc, w + bo[l], H, wv, lane);
+        __syncthreads();
+    }
+    // layer 4: 49 outputs; wave wv takes rows 16 wv .. 16 wv + 15
+    f32x4 o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int ks = 0; ks < kHid / 32; ++ks) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&H[16 * wv + lr][32 * ks + lk]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = 16 * j + lr;
+            bf16x8 b;
+            if (col < kOut) {
+                b = *reinterpret_cast<const bf16x8*>(wt + kW4 + col * kHid + 32 * ks + lk);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) b[e] = zero;
+            }
+            o[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o[j], 0, 0, 0);
+        }
+    }
+    // softmax of each row over the 16 lanes (x 4 tiles) that hold it
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = row0 + 16 * wv + 4 * (lane >> 4) + r;
+        float z[4], mx = -INFINITY;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = 16 * j + lr;
+            z[j] = col < kOut ? o[j][r] + w[kB4 + col] : -INFINITY;
+            mx = fmaxf(mx, z[j]);
+        }
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) mx = fmaxf(mx, __shfl_xor(mx, d, 64));
+        float e[4], sum = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            e[j] = 16 * j + lr < kOut ? __expf(z[j] - mx) : 0.f;
+            sum += e[j];
+        }
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) sum += __shfl_xor(sum, d, 64);
+        if (row < B) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = 16 * j + lr;
+                if (col < kOut) g[(long)row * kOut + col] = e[j] / sum;
+            }
+        }
+    }
+}
+
 }  // namespace
 }  // namespace mdlg
 
@@ -371,7 +525,6 @@ hipError_t gemm(int epi, int M, int N, int K, const bf16* A, long a_sm, long a_s
         case EPI_STORE: launch_ab<EPI_STORE>(am, bm, grid, st, g); break;
         case EPI_BIAS_SILU: launch_ab<EPI_BIAS_SILU>(am, bm, grid, st, g); break;
         case EPI_BIAS: launch_ab<EPI_BIAS>(am, bm, grid, st, g); break;
-        case EPI_SILU_H: launch_ab<EPI_SILU_H>(am, bm, grid, st, g); break;
         default: launch_ab<EPI_SILU_BWD>(am, bm, grid, st, g); break;
     }
     if (split > 1) {
@@ -383,16 +536,16 @@ hipError_t gemm(int epi, int M, int N, int K, const bf16* A, long a_sm, long a_s
 
 unsigned nblk(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-// Forward pass on B inputs already in m->xb; leaves h1..h3 and the logits z4,
-// and for training (keep_z) the pre-activations z1..z3.
-hipError_t forward(mdlg_mlp* m, int B, bool keep_z, hipStream_t st) {
+// Forward pass for training on B inputs already in m->xb: pre-activations
+// z1..z3, activations h1..h3 and the logits z4 (inference uses k_mlp_infer).
+hipError_t forward(mdlg_mlp* m, int B, hipStream_t st) {
     const long in[4] = {kIn, kHid, kHid, kHid};
     const long wo[4] = {kW1, kW2, kW3, kW4};
     const long bo[4] = {kB1, kB2, kB3, kB4};
     hipError_t e = hipSuccess;
     const bf16* a = m->xb;
     for (int l = 0; l < 3 && e == hipSuccess; ++l) {
-        e = gemm(keep_z ? EPI_BIAS_SILU : EPI_SILU_H, B, kHid, (int)in[l], a, in[l], 1, m->wt + wo[l], 1, in[l],
+        e = gemm(EPI_BIAS_SILU, B, kHid, (int)in[l], a, in[l], 1, m->wt + wo[l], 1, in[l],
                  m->w + bo[l], m->Z[l], kHid, m->H[l], kHid, st);
         a = m->H[l];
     }
@@ -526,15 +679,9 @@ extern "C" mdlg_status mdlg_mlp_forward(mdlg_mlp* m, const float* x, int32_t B, 
     if (s != MDLG_OK) return s;
     if (!x || !g_out) return fail(MDLG_EINVAL, "mdlg_mlp_forward: NULL argument");
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_prep_input, dim3(nblk((long)B * kIn)), dim3(256), 0, st, x, B, m->xb);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward(m, B, false, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_softmax, dim3((B + 3) / 4), dim3(256), 0, st, (const float*)m->z4, (const float*)nullptr, B,
-                           g_out, (bf16*)nullptr, (float*)nullptr);
-        e = hipGetLastError();
-    }
-    MDLG_HIP(e);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((B + kFB - 1) / kFB)), dim3(256), 0, st, x, B,
+                       (const bf16*)m->wt, (const float*)m->w, g_out);
+    MDLG_HIP(hipGetLastError());
     return MDLG_OK;
 }
 
@@ -546,7 +693,7 @@ extern "C" mdlg_status mdlg_mlp_gradient(mdlg_mlp* m, const float* x, const floa
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_prep_input, dim3(nblk((long)B * kIn)), dim3(256), 0, st, x, B, m->xb);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward(m, B, true, st);
+    if (e == hipSuccess) e = forward(m, B, st);
     if (e == hipSuccess) e = backward(m, target, B, st);
     if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && grad) e = hipMemcpyAsync(grad, m->grad, sizeof(float) * kParams, hipMemcpyDeviceToDevice, st);
@@ -563,7 +710,7 @@ extern "C" mdlg_status mdlg_mlp_train_step(mdlg_mlp* m, const float* x, const fl
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_prep_input, dim3(nblk((long)B * kIn)), dim3(256), 0, st, x, B, m->xb);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward(m, B, true, st);
+    if (e == hipSuccess) e = forward(m, B, st);
     if (e == hipSuccess) e = backward(m, target, B, st);
     if (e == hipSuccess) {
         m->step += 1;
