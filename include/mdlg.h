@@ -93,11 +93,13 @@ typedef struct {
                                cells                                              */
     int32_t gather_batch;   /* kernel 1: neighbour loads issued per batch, 0 = 8;
                                4, 8 or 16                                         */
-    int32_t fuse_steps;     /* kernel 3: 0 = two consecutive ordinary steps per
-                               launch where possible (square tiles of cells
-                               with a one-cell halo; positions and velocities
-                               of the first step stay in LDS), 1 = one step per
-                               launch.  Results are the same either way.        */
+    int32_t fuse_steps;     /* kernel 3: two consecutive ordinary steps per
+                               launch (square tiles of cells with a one-cell
+                               halo; the first step's positions stay in LDS):
+                               0 = where the tiles are at least 16 cells wide
+                               (dilute systems, where the halo is cheap),
+                               1 = never, 2 = wherever the geometry allows.
+                               Results are the same bit for bit.               */
 } lj_params;
 
 typedef struct lj_md lj_md; /* opaque handle; owns all device state */

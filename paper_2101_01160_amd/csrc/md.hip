@@ -932,6 +932,7 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
 // bit.  Velocities go to a second buffer: other tiles still read the old ones.
 constexpr int kPairCap = 768;   // staged particles of one tile, owned + halo
 constexpr int kStep2BS = 512;   // threads of the two-step kernel
+constexpr int kPairAutoT = 16;  // smallest tile side (cells) of the default two-step choice
 constexpr int kPairSeg = 104;   // row segments of one tile: 3 pT + 6 <= 102
 
 // Per tile, after the neighbour lists: the staged slots (owned rows, then the
@@ -1907,7 +1908,7 @@ mdlg_status check_params(const lj_params& p, int r) {
     if (p.step_kernel < 0 || p.step_kernel > 3) return bad("step_kernel must be 0, 1, 2 or 3");
     if (p.gather_batch != 0 && p.gather_batch != 4 && p.gather_batch != 8 && p.gather_batch != 16)
         return bad("gather_batch must be 0, 4, 8 or 16");
-    if (p.fuse_steps != 0 && p.fuse_steps != 1) return bad("fuse_steps must be 0 or 1");
+    if (p.fuse_steps < 0 || p.fuse_steps > 2) return bad("fuse_steps must be 0, 1 or 2");
     return MDLG_OK;
 }
 
@@ -2025,7 +2026,11 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     // two-step tiles: about 460 staged particles on average, so that one
     // block of kStep2BS threads advances a tile in one pass per step; a ring
     // of distinct cells needs nc >= pT + 2
-    md->two_step = md->variant == 3 && p[0].fuse_steps == 0;
+    // (fuse_steps 0: only where tiles are at least kPairAutoT cells wide, so
+    // that the halo adds at most ~30% to the first step; 2: wherever the
+    // geometry allows)
+    md->two_step = md->variant == 3 && p[0].fuse_steps != 1;
+    const int tmin = p[0].fuse_steps == 2 ? 2 : kPairAutoT;
     {
         long long pt = 0;
         for (int r = 0; r < n_rep && md->two_step; ++r) {
@@ -2033,7 +2038,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             const double ppc = std::max((double)d.n / ((double)d.nc * d.nc), 1e-9);
             int T = (int)std::floor(std::sqrt(460.0 / ppc)) - 2;
             T = std::min(std::min(T, 32), d.nc - 2);
-            if (T < 2) {
+            if (T < tmin) {
                 md->two_step = false;
                 break;
             }

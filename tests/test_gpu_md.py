@@ -332,23 +332,23 @@ def test_autotuner_returns_runnable_params(tmp_path, monkeypatch):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n,phi,kT,kw", [
-    (512, 0.0784, 20.0, {}),
-    (2000, 0.4, 20.0, {"block_size": 128}),
-    (700, 0.4, 20.0, {"skin": 0.2, "rebuild_every": 3}),
-    (3000, 0.2, 1.0, {"force_bits": 32}),
-    (20000, 0.0784, 20.0, {"block_size": 512}),
+@pytest.mark.parametrize("n,phi,kT,fuse,kw", [
+    (512, 0.0784, 20.0, 0, {}),
+    (2000, 0.4, 20.0, 2, {"block_size": 128}),
+    (700, 0.4, 20.0, 2, {"skin": 0.2, "rebuild_every": 3}),
+    (3000, 0.2, 1.0, 2, {"force_bits": 32}),
+    (20000, 0.0784, 20.0, 0, {"block_size": 512}),
 ])
-def test_two_steps_per_launch_equal_one(n, phi, kT, kw):
+def test_two_steps_per_launch_equal_one(n, phi, kT, fuse, kw):
     """Two ordinary steps per launch (tiles with a staged halo) give the same
     state, bit for bit, as one step per launch, with and without the fused
     coarse-graining."""
-    print(f"two-step n={n} phi={phi} kT={kT} {kw}", flush=True)
+    print(f"two-step n={n} phi={phi} kT={kT} fuse={fuse} {kw}", flush=True)
     pos0, vel0, L = mi.initial_state(n, phi, kT, 5)
     out = []
-    for fuse in (0, 1):
-        sysm = gpu_system(pos0, vel0, L, fuse_steps=fuse, **kw)
-        assert sysm.info()["steps_per_launch"] == (2 if fuse == 0 else 1)
+    for f in (fuse, 1):
+        sysm = gpu_system(pos0, vel0, L, fuse_steps=f, **kw)
+        assert sysm.info()["steps_per_launch"] == (2 if f != 1 else 1)
         acc = sysm.attach_cg(max(7, int(L / 2.0)), 10)
         sysm.step(13)
         sysm.step(131)
@@ -365,9 +365,13 @@ def test_two_step_batched_replicas_equal_single():
     states = [mi.initial_state(n, phi, kT, 11 + i) for i, (n, phi, kT) in enumerate(specs)]
     pos = np.concatenate([s[0] for s in states])
     vel = np.concatenate([s[1] for s in states])
-    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10) for s in states]
+    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10, fuse_steps=2) for s in states]
     batch = m.LJSystem(_cuda(pos), _cuda(vel), params=params)
     assert batch.info()["steps_per_launch"] == 2
+    # by default the dense replicas keep one step per launch
+    dflt = m.LJSystem(_cuda(pos), _cuda(vel), params=[m.lj_params(p.n, p.box_l, rebuild_every=10) for p in params])
+    assert dflt.info()["steps_per_launch"] == 1
+    dflt.close()
     batch.step(55)
     bpos = _np(batch.state()[0])
     batch.close()
