@@ -14,7 +14,10 @@ Follows
   * Eq.(poisson_v2), Eq.(f_eq_wsg) and the N_c definition below it:
     Poisson-WSG f^eq as sum_c e^-lam lam^c / c! prod_a f^{c,eq}_{i,a}.
   * Eq.(fourth_order), Eq.(lambda_eq) and the printed roots lambda_{1,2}.
-  * Eq.(kullback_leibler): KL divergence.
+  * Eq.(gaussian_df) and Eq.(poisson_v2) with Eq.(p_wsg_one): the
+    one-axis displacement PDFs, integrated over the bins X_k of a histogram
+    (the comparison of Fig. 2).
+  * Eq.(k_Xi) and Eq.(kullback_leibler): element-wise and summed KL divergence.
 """
 from __future__ import annotations
 
@@ -157,11 +160,76 @@ def lambda_from_moments(mu2, mu4, branch: int = 2):
     return (roots[0] if branch == 1 else roots[1]), r
 
 
+# ---------------------------------------------------- displacement PDF ---
+
+def bin_edges(h, n_bin):
+    """Edges of the histogram intervals X_k = [(k - n_bin/2) h, (k + 1 - n_bin/2) h)."""
+    return [(mp.mpf(k) - mp.mpf(n_bin) / 2) * mp.mpf(h) for k in range(n_bin + 1)]
+
+
+def _normal_masses(edges, mean, var):
+    """Masses of a normal law (mean, var) on the bins between consecutive edges,
+    then below the first edge and at or above the last: [n_bin + 2]."""
+    s = mp.sqrt(2 * mp.mpf(var))
+    E = [mp.erf((e - mp.mpf(mean)) / s) for e in edges]
+    inner = [(E[k + 1] - E[k]) / 2 for k in range(len(edges) - 1)]
+    return inner + [(1 + E[0]) / 2, (1 - E[-1]) / 2]
+
+
+def pdf_bins(msd, lam, mean, h, n_bin):
+    """Probability of each bin X_k under the single Gaussian P^G and under the
+    Poisson WSG P^WSG of one axis (Eq.(gaussian_df); Eq.(poisson_v2) with
+    P^c of Eq.(p_wsg_one), whose variance is msd (c + 1) / (lam + 1)).
+    msd is <(delta x)^2> about the mean displacement `mean` (u dt).
+    Entries [n_bin] and [n_bin + 1] are the masses below and above the range.
+    lam = 0 gives P^WSG = P^G.  Returns (pG, pW) float64 [n_bin + 2]."""
+    edges = bin_edges(h, n_bin)
+    pg = _normal_masses(edges, mean, msd)
+    lam_m = mp.mpf(lam)
+    lo, hi = poisson_window(lam)
+    pw = [mp.mpf(0)] * (n_bin + 2)
+    for c in range(lo, hi + 1):
+        w = mp.exp(-lam_m) * (lam_m ** c if c > 0 else mp.mpf(1)) / mp.factorial(c)
+        pc = _normal_masses(edges, mean, mp.mpf(msd) * (c + 1) / (lam_m + 1))
+        pw = [a + w * b for a, b in zip(pw, pc)]
+    return np.array([float(x) for x in pg]), np.array([float(x) for x in pw])
+
+
+def pdf_measured(hist):
+    """P^MD(X_k): the counts of one or more histograms [..., n_bin + 2] pooled
+    (summed over the leading axes) and divided by their total."""
+    h = np.asarray(hist, dtype=np.int64).reshape(-1, np.shape(hist)[-1]).sum(axis=0)
+    tot = int(h.sum())
+    if tot <= 0:
+        raise ValueError("empty histogram")
+    return h.astype(np.float64) / float(tot)
+
+
 # ----------------------------------------------------------------- KL ---
 
+def kl_elementwise(R, Q):
+    """K(X_i) = R(X_i) log(R(X_i) / Q(X_i)), Eq.(k_Xi), at 50 digits.  A term
+    with R_i = 0 is 0 (the limit of r log r); R_i > 0 with Q_i = 0 is +inf."""
+    out = []
+    for r, q in zip(np.asarray(R, dtype=np.float64), np.asarray(Q, dtype=np.float64)):
+        if r == 0.0:
+            out.append(0.0)
+        elif q == 0.0:
+            out.append(math.inf)
+        else:
+            out.append(float(mp.mpf(r) * mp.log(mp.mpf(r) / mp.mpf(q))))
+    return np.array(out)
+
+
 def kl_divergence(R, Q):
-    """D_KL(R || Q) = sum_i R_i log(R_i / Q_i), Eq.(kullback_leibler); terms with R_i = 0 vanish."""
+    """D_KL(R || Q) = sum_i K(X_i), Eq.(kullback_leibler), summed at 50 digits."""
+    K = kl_elementwise(R, Q)
+    if np.isinf(K).any():
+        return math.inf
     R = np.asarray(R, dtype=np.float64)
     Q = np.asarray(Q, dtype=np.float64)
-    m = R > 0
-    return float(np.sum(R[m] * np.log(R[m] / Q[m])))
+    acc = mp.mpf(0)
+    for r, q in zip(R, Q):
+        if r > 0:
+            acc += mp.mpf(r) * mp.log(mp.mpf(r) / mp.mpf(q))
+    return float(acc)

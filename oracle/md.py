@@ -57,6 +57,8 @@ def _load():
     lib.orc_coarse_grain_literal.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, _i32p,
                                              C.c_int64, _dp, C.c_int64, _dp, C.c_int64, _i64p,
                                              C.c_void_p]
+    lib.orc_displacement_hist.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_int32, _dp, C.c_void_p, _dp,
+                                          C.c_void_p, _i64p]
     lib.orc_md_run.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
                                C.c_int32, C.c_int64, _dp, _dp, _i64p, C.POINTER(_CG), C.c_void_p,
                                C.c_int64]
@@ -177,3 +179,35 @@ def coarse_grain_literal(lx, L, pos_prev, pos_cur, k_prev=0, k_cur=1, u=(0.0, 0.
     lib.orc_coarse_grain_literal(lx, L, u[0], u[1], vtab, pos_prev.shape[0], pos_prev, k_prev, pos_cur,
                                  k_cur, counts, _ptr(n_event))
     return counts, n_event
+
+
+def displacement_hist(L, h, n_bin, pos_prev, pos_cur, img_prev=None, img_cur=None, hist=None):
+    """Per-axis histogram of the box-frame displacements of one snapshot pair
+    (bins of width h, see orc_displacement_hist).  Returns hist [2, n_bin + 2] int64."""
+    lib = _load()
+    pos_prev, pos_cur = _f64(pos_prev), _f64(pos_cur)
+    hist = np.zeros((2, n_bin + 2), dtype=np.int64) if hist is None else hist
+    ip = None if img_prev is None else _i64(img_prev)
+    ic = None if img_cur is None else _i64(img_cur)
+    lib.orc_displacement_hist(pos_prev.shape[0], float(L), float(h), int(n_bin), pos_prev, _ptr(ip), pos_cur,
+                              _ptr(ic), hist)
+    return hist
+
+
+def displacement_hist_series(offsets, box_l, pos, img, lags, h, n_bin):
+    """Displacement histograms of a stacked trajectory pos [P, n_tot, 2], img [P, n_tot, 2]:
+    for replica r (particles offsets[r] .. offsets[r+1]-1, box side box_l[r]) and lag
+    lags[s] (bin width h[s]), every snapshot pair (p - lag, p).
+    Returns [n_rep, n_lag, 2, n_bin + 2] int64."""
+    offsets = [int(o) for o in offsets]
+    n_rep, n_snap = len(offsets) - 1, pos.shape[0]
+    out = np.zeros((n_rep, len(lags), 2, n_bin + 2), dtype=np.int64)
+    for r in range(n_rep):
+        a, b = offsets[r], offsets[r + 1]
+        if b == a:
+            continue
+        for s, lag in enumerate(lags):
+            for p in range(lag, n_snap):
+                displacement_hist(box_l[r], h[s], n_bin, pos[p - lag, a:b], pos[p, a:b], img[p - lag, a:b],
+                                  img[p, a:b], hist=out[r, s])
+    return out

@@ -20,6 +20,9 @@
  *    "Molecular dynamics lattice gas method" section: particle j adds one to
  *    n_i(x, t) when it sits in lattice cell x at time t and sat in cell x - v_i
  *    at time t - dt_cg.
+ *  - Displacement histogram: the binned one-particle displacement PDF
+ *    P^MD(X_i) that the displacement-PDF figure (Fig. 2) sets beside the
+ *    single-Gaussian Eq.(gaussian_df) and the Poisson WSG Eq.(poisson_v2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -316,6 +319,38 @@ void orc_coarse_grain_literal(int32_t lx, double L, double ux, double uy, const 
         }
     }
     counts[NQ] += n - total;
+}
+
+/* ------------------------------------------------ displacement PDF --- */
+
+/* Histogram of the box-frame displacements of one snapshot pair, per axis.
+ * delta = (x_cur - x_prev) + L (img_cur - img_prev).  The n_bin intervals
+ * X_k = [(k - n_bin/2) h, (k + 1 - n_bin/2) h), k = 0 .. n_bin - 1, tile
+ * [-n_bin h / 2, n_bin h / 2); a displacement falls in X_k with
+ * k = floor(delta * (1 / h) + n_bin / 2), evaluated in that order in FP64.
+ * hist [2][n_bin + 2] (axis x, then y) is added to: index k for X_k, n_bin
+ * below the range, n_bin + 1 at or above it (and for a non-number). */
+void orc_displacement_hist(int64_t n, double L, double h, int32_t n_bin, const double* pos_prev,
+                           const int64_t* img_prev, const double* pos_cur, const int64_t* img_cur,
+                           int64_t* hist) {
+    double inv_h = 1.0 / h;
+    double half = 0.5 * (double)n_bin;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int a = 0; a < 2; ++a) {
+            int64_t ip = img_prev ? img_prev[2 * j + a] : 0;
+            int64_t ic = img_cur ? img_cur[2 * j + a] : 0;
+            double delta = (pos_cur[2 * j + a] - pos_prev[2 * j + a]) + L * (double)(ic - ip);
+            double t = delta * inv_h + half;
+            int64_t k;
+            if (t >= 0.0 && t < (double)n_bin)
+                k = (int64_t)floor(t);
+            else if (t < 0.0)
+                k = n_bin;
+            else
+                k = (int64_t)n_bin + 1;
+            hist[(int64_t)a * (n_bin + 2) + k] += 1;
+        }
+    }
 }
 
 /* -------------------------------------------------------- integration --- */
