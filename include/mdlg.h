@@ -50,6 +50,7 @@ typedef int32_t mdlg_status;
 #define MDLG_ECAPACITY (-7)   /* a neighbour list overflowed its capacity        */
 
 #define MDLG_NQ 49            /* D2Q49 lattice velocities, |v_x|, |v_y| <= 3     */
+#define MDLG_HIST_MAX_BINS 4094 /* displacement-histogram bins (2 more count the tails) */
 #define MDLG_NCOUNTS 50       /* 49 velocities + 1 overflow bin (|v_a| > 3)      */
 #define MDLG_NMOMENTS 5       /* samples, sum d^2, sum d^4, sum d_x, sum d_y     */
 
@@ -305,6 +306,58 @@ mdlg_status mdlg_feq_gauss(double a2, const double* u, double* g_out);
  * with variance a2 (c+1)/(lambda+1).  The sum is truncated where the
  * remaining Poisson weight is below 1e-20.  lambda = 0 gives mdlg_feq_gauss. */
 mdlg_status mdlg_feq_wsg(double a2, double lambda, const double* u, double* g_out);
+
+/* ------------------------------------------------------------------------ */
+/* Displacement PDFs and the KL divergence (Fig. 2)                          */
+/* ------------------------------------------------------------------------ */
+
+/* Histograms of the one-particle box-frame displacements of a stored
+ * trajectory: the binned displacement PDF P^MD(X_k) compared with the single
+ * Gaussian (Eq.(gaussian_df)) and the Poisson WSG (Eq.(poisson_v2)).
+ * Replica r owns particles offsets[r] .. offsets[r+1]-1 (host [n_rep + 1],
+ * offsets[0] = 0) in a box of side box_l[r] (host).  pos (device
+ * [n_snap][n_tot][2] float64, wrapped) and img (device [n_snap][n_tot][2]
+ * int32 image counts) stack 2 <= n_snap <= 2^24 snapshots.  For lag
+ * lags[s] (host [n_lag], 1 .. n_snap - 1, n_lag <= 64) and every pair
+ * (p - lag, p), each particle's displacement per axis
+ *   delta = (x_p - x_{p-lag}) + L (img_p - img_{p-lag})
+ * falls in bin k = floor(delta * (1 / h) + n_bin / 2) (FP64, each operation
+ * rounded once), h = bin_width[s] (host [n_lag], > 0): the intervals
+ * X_k = [(k - n_bin/2) h, (k + 1 - n_bin/2) h), k < n_bin, tile
+ * [-n_bin h / 2, n_bin h / 2).  Adds to hist (device int64
+ * [n_rep][n_lag][2][n_bin + 2], axis x then y): [k] for X_k, [n_bin] below
+ * the range, [n_bin + 1] at or above it.  1 <= n_bin <= MDLG_HIST_MAX_BINS.
+ * Counts are exact integers, independent of the launch.  Synchronises the
+ * stream. */
+mdlg_status mdlg_displacement_hist(int32_t n_rep, const int64_t* offsets, const double* box_l,
+                                   int32_t n_snap, const double* pos, const int32_t* img,
+                                   int32_t n_lag, const int32_t* lags, const double* bin_width,
+                                   int32_t n_bin, int64_t* hist, void* stream);
+
+/* Probability of each histogram bin under the one-axis single Gaussian
+ * P^G (Eq.(gaussian_df), variance msd) and the Poisson WSG P^WSG
+ * (Eq.(poisson_v2) with P^c of Eq.(p_wsg_one), variance msd (c + 1) /
+ * (lambda + 1)), both centred on `mean` (the mean displacement u dt, in the
+ * units of h).  msd is the second moment about the mean, > 0.  The bins are
+ * those of mdlg_displacement_hist (n_bin, width h); [n_bin] and [n_bin + 1]
+ * receive the masses below and above the range.  The Poisson sum uses the
+ * window of mdlg_feq_wsg; lambda = 0 gives P^WSG = P^G.  Outputs host
+ * [n_bin + 2]; either may be NULL. */
+mdlg_status mdlg_pdf_bins(double msd, double lambda, double mean, double h, int32_t n_bin,
+                          double* p_gauss, double* p_wsg);
+
+/* P^MD(X_k): n_hist histograms of n counts each (host [n_hist][n], e.g. the
+ * two axes of one lag) summed bin by bin and divided by their total.
+ * p_out host [n].  EINVAL for negative counts or an empty total. */
+mdlg_status mdlg_pdf_measured(const int64_t* hist, int32_t n_hist, int32_t n, double* p_out);
+
+/* Element-wise Kullback-Leibler divergence K(X_i) = R_i log(R_i / Q_i)
+ * (Eq.(k_Xi)) into k_out (host [n], may be NULL) and its sum D_KL(R || Q)
+ * (Eq.(kullback_leibler), compensated, index order) into d_kl (may be NULL).
+ * A term with R_i = 0 is 0; R_i > 0 with Q_i = 0 is +inf (and so is D_KL).
+ * r, q host [n], finite and >= 0; they are not renormalised. */
+mdlg_status mdlg_kl_divergence(const double* r, const double* q, int32_t n, double* k_out,
+                               double* d_kl);
 
 /* ------------------------------------------------------------------------ */
 /* Surrogate network for f_eq (device, BF16 matrix cores)                    */

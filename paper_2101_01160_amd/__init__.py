@@ -29,6 +29,7 @@ __all__ = [
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
+    "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy", "SurrogateMLP", "MLP_NPARAMS",
 ]
@@ -224,6 +225,56 @@ def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, mome
         int(uu.shape[0]), uu.ctypes.data_as(C.c_void_p), None if lo is None else lo.ctypes.data_as(C.c_void_p),
         _dev(counts, torch.int64, (n_rep, lg.size, uu.shape[0], 50), "counts"),
         _dev(moments, torch.float64, (n_rep, lg.size, 5), "moments"), _stream(stream)))
+
+
+def mdlg_displacement_hist(offsets, box_l, pos, img, lags, bin_width, n_bin, hist, stream=None):
+    """pos: torch float64 [P, n_tot, 2], img: torch int32 [P, n_tot, 2] on the GPU;
+    hist: torch int64 [n_rep, n_lag, 2, n_bin + 2] on the GPU (added to)."""
+    torch = _torch()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_rep = off.size - 1
+    box = _host(box_l, np.float64, n_rep)
+    lg = np.ascontiguousarray(lags, dtype=np.int32).ravel()
+    bw = _host(bin_width, np.float64, lg.size)
+    P, n_tot = int(pos.shape[0]), int(pos.shape[1])
+    if n_tot != int(off[-1]):
+        raise ValueError("pos holds a different particle count than offsets")
+    _abi.check(_abi.lib().mdlg_displacement_hist(
+        int(n_rep), off.ctypes.data_as(C.c_void_p), box.ctypes.data_as(C.c_void_p), P,
+        _dev(pos, torch.float64, (P, n_tot, 2), "pos"), _dev(img, torch.int32, (P, n_tot, 2), "img"),
+        int(lg.size), lg.ctypes.data_as(C.c_void_p), bw.ctypes.data_as(C.c_void_p), int(n_bin),
+        _dev(hist, torch.int64, (n_rep, lg.size, 2, int(n_bin) + 2), "hist"), _stream(stream)))
+
+
+def mdlg_pdf_bins(msd, lam, mean, h, n_bin):
+    """(P^G, P^WSG) bin probabilities, float64 [n_bin + 2] each (tails last)."""
+    pg = np.zeros(int(n_bin) + 2)
+    pw = np.zeros(int(n_bin) + 2)
+    _abi.check(_abi.lib().mdlg_pdf_bins(float(msd), float(lam), float(mean), float(h), int(n_bin),
+                                        pg.ctypes.data_as(C.c_void_p), pw.ctypes.data_as(C.c_void_p)))
+    return pg, pw
+
+
+def mdlg_pdf_measured(hist):
+    """P^MD: host histograms [..., n] pooled over the leading axes and normalised."""
+    h = np.ascontiguousarray(hist, dtype=np.int64)
+    n = int(h.shape[-1])
+    h = h.reshape(-1, n)
+    p = np.zeros(n)
+    _abi.check(_abi.lib().mdlg_pdf_measured(h.ctypes.data_as(C.c_void_p), int(h.shape[0]), n,
+                                            p.ctypes.data_as(C.c_void_p)))
+    return p
+
+
+def mdlg_kl_divergence(r, q):
+    """(K(X_i) [n], D_KL(R || Q))."""
+    rr = np.ascontiguousarray(r, dtype=np.float64).ravel()
+    qq = _host(q, np.float64, rr.size)
+    k = np.zeros(rr.size)
+    d = C.c_double()
+    _abi.check(_abi.lib().mdlg_kl_divergence(rr.ctypes.data_as(C.c_void_p), qq.ctypes.data_as(C.c_void_p),
+                                             int(rr.size), k.ctypes.data_as(C.c_void_p), C.byref(d)))
+    return k, d.value
 
 
 # ------------------------------------------------------------ equilibria ---

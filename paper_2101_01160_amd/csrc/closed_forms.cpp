@@ -149,3 +149,116 @@ extern "C" mdlg_status mdlg_feq_wsg(double a2, double lambda, const double* u, d
     }
     return MDLG_OK;
 }
+
+// ------------------------------------------------------ displacement PDF ---
+
+namespace {
+
+// Mass of N(mean, s^2) on [a, b) (a may be -inf, b +inf).  Each case keeps the
+// erfc arguments non-negative, so tail bins keep their relative accuracy.
+double normal_mass(double a, double b, double mean, double s) {
+    const double za = (a - mean) / s * kInvSqrt2, zb = (b - mean) / s * kInvSqrt2;
+    if (za >= 0.0) return 0.5 * (std::erfc(za) - std::erfc(zb));
+    if (zb <= 0.0) return 0.5 * (std::erfc(-zb) - std::erfc(-za));
+    return 1.0 - 0.5 * (std::erfc(-za) + std::erfc(zb));
+}
+
+// acc[k] += w * mass of bin k (k < n_bin), acc[n_bin] below, acc[n_bin + 1] above.
+void normal_bins(double var, double mean, double h, int n_bin, double w, double* acc) {
+    const double s = std::sqrt(var);
+    const double half = 0.5 * (double)n_bin;
+    double lo = (0.0 - half) * h;
+    for (int k = 0; k < n_bin; ++k) {
+        const double hi = ((double)(k + 1) - half) * h;
+        acc[k] += w * normal_mass(lo, hi, mean, s);
+        lo = hi;
+    }
+    acc[n_bin] += w * normal_mass(-INFINITY, (0.0 - half) * h, mean, s);
+    acc[n_bin + 1] += w * normal_mass(((double)n_bin - half) * h, INFINITY, mean, s);
+}
+
+}  // namespace
+
+extern "C" mdlg_status mdlg_pdf_bins(double msd, double lambda, double mean, double h, int32_t n_bin,
+                                     double* p_gauss, double* p_wsg) {
+    const char* who = "mdlg_pdf_bins: ";
+    if (!p_gauss && !p_wsg) return mdlg::fail(MDLG_EINVAL, std::string(who) + "both outputs are NULL");
+    if (!(msd > 0.0) || !std::isfinite(msd) || !(h > 0.0) || !std::isfinite(h) || !std::isfinite(mean) ||
+        !(lambda >= 0.0) || !(lambda <= 1e8))
+        return mdlg::fail(MDLG_EINVAL, std::string(who) + "need finite msd > 0, h > 0, mean and 0 <= lambda <= 1e8");
+    if (n_bin < 1 || n_bin > MDLG_HIST_MAX_BINS)
+        return mdlg::fail(MDLG_EINVAL, std::string(who) + "n_bin must be in [1, MDLG_HIST_MAX_BINS]");
+    if (p_gauss) {
+        for (int k = 0; k < n_bin + 2; ++k) p_gauss[k] = 0.0;
+        normal_bins(msd, mean, h, n_bin, 1.0, p_gauss);
+    }
+    if (p_wsg) {
+        for (int k = 0; k < n_bin + 2; ++k) p_wsg[k] = 0.0;
+        if (lambda == 0.0) {
+            normal_bins(msd, mean, h, n_bin, 1.0, p_wsg);
+            return MDLG_OK;
+        }
+        // the Poisson window of mdlg_feq_wsg; component c has variance msd (c + 1) / (lambda + 1)
+        long lo = (long)std::floor(lambda - 12.0 * std::sqrt(lambda) - 10.0);
+        if (lo < 0) lo = 0;
+        long hi = (long)std::ceil(lambda + 12.0 * std::sqrt(lambda) + 40.0);
+        const double ll = std::log(lambda);
+        for (long c = lo; c <= hi; ++c) {
+            const double w = std::exp((double)c * ll - lambda - std::lgamma((double)c + 1.0));
+            if (w == 0.0) continue;
+            normal_bins(msd * ((double)c + 1.0) / (lambda + 1.0), mean, h, n_bin, w, p_wsg);
+        }
+    }
+    return MDLG_OK;
+}
+
+extern "C" mdlg_status mdlg_pdf_measured(const int64_t* hist, int32_t n_hist, int32_t n, double* p_out) {
+    const char* who = "mdlg_pdf_measured: ";
+    if (!hist || !p_out || n_hist < 1 || n < 1)
+        return mdlg::fail(MDLG_EINVAL, std::string(who) + "NULL argument, n_hist < 1 or n < 1");
+    int64_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        int64_t s = 0;
+        for (int j = 0; j < n_hist; ++j) {
+            const int64_t c = hist[(int64_t)j * n + k];
+            if (c < 0) return mdlg::fail(MDLG_EINVAL, std::string(who) + "negative count");
+            s += c;
+        }
+        p_out[k] = (double)s;
+        total += s;
+    }
+    if (total <= 0) return mdlg::fail(MDLG_EINVAL, std::string(who) + "empty histogram");
+    for (int k = 0; k < n; ++k) p_out[k] /= (double)total;
+    return MDLG_OK;
+}
+
+extern "C" mdlg_status mdlg_kl_divergence(const double* r, const double* q, int32_t n, double* k_out,
+                                          double* d_kl) {
+    const char* who = "mdlg_kl_divergence: ";
+    if (!r || !q || n < 1) return mdlg::fail(MDLG_EINVAL, std::string(who) + "NULL argument or n < 1");
+    double s = 0.0, comp = 0.0;  // Neumaier-compensated sum in index order
+    bool inf = false;
+    for (int i = 0; i < n; ++i) {
+        if (!(r[i] >= 0.0) || !std::isfinite(r[i]) || !(q[i] >= 0.0) || !std::isfinite(q[i]))
+            return mdlg::fail(MDLG_EINVAL, std::string(who) + "probabilities must be finite and >= 0");
+        double k;
+        if (r[i] == 0.0) {
+            k = 0.0;  // r log r -> 0
+        } else if (q[i] == 0.0) {
+            k = INFINITY;
+            inf = true;
+        } else {
+            const double ratio = r[i] / q[i];
+            k = (std::isnormal(ratio) && std::isfinite(ratio)) ? r[i] * std::log(ratio)
+                                                                : r[i] * (std::log(r[i]) - std::log(q[i]));
+        }
+        if (k_out) k_out[i] = k;
+        if (!inf) {
+            const double t = s + k;
+            comp += std::fabs(s) >= std::fabs(k) ? (s - t) + k : (k - t) + s;
+            s = t;
+        }
+    }
+    if (d_kl) *d_kl = inf ? INFINITY : s + comp;
+    return MDLG_OK;
+}

@@ -105,3 +105,49 @@ def test_invalid_arguments_raise():
         m.mdlg_lambda_from_moments(0.0, 1.0)
     with pytest.raises(m.MDLGError):
         m.mdlg_feq_measured(np.zeros(50, np.int64), 0, 1)
+
+
+@pytest.mark.parametrize("msd,lam,mean,h,n_bin", [(1.0, 0.0, 0.0, 0.25, 41), (0.0123, 0.7, 0.003, 0.02, 31),
+                                                  (2.5, 3.0, -0.4, 0.3, 60), (1e-3, 12.0, 0.0, 0.01, 17),
+                                                  (4.0, 0.2, 1.0, 0.05, 1)])
+def test_pdf_bins_match_oracle(msd, lam, mean, h, n_bin):
+    import paper_2101_01160_amd as m
+    pg, pw = m.mdlg_pdf_bins(msd, lam, mean, h, n_bin)
+    rg, rw = cf.pdf_bins(msd, lam, mean, h, n_bin)
+    for got, ref in ((pg, rg), (pw, rw)):
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-16)
+    assert pg.sum() == pytest.approx(1.0, abs=1e-14) and pw.sum() == pytest.approx(1.0, abs=1e-14)
+
+
+def test_pdf_measured_and_kl_match_oracle():
+    import paper_2101_01160_amd as m
+    rng = np.random.default_rng(6)
+    hist = rng.integers(0, 1000, (2, 3, 2, 45)).astype(np.int64)
+    hist[..., 7] = 0
+    assert np.allclose(m.mdlg_pdf_measured(hist), cf.pdf_measured(hist), rtol=1e-15, atol=0)
+    r = cf.pdf_measured(hist)
+    q = cf.pdf_bins(0.8, 1.5, 0.0, 0.1, 43)[1]
+    k, d = m.mdlg_kl_divergence(r, q)
+    assert np.allclose(k, cf.kl_elementwise(r, q), rtol=1e-13, atol=1e-300)
+    assert k[7] == 0.0
+    assert d == pytest.approx(cf.kl_divergence(r, q), rel=1e-13)
+    k, d = m.mdlg_kl_divergence(q, q)
+    assert d == 0.0 and not k.any()
+    k, d = m.mdlg_kl_divergence([0.5, 0.5], [1.0, 0.0])
+    assert np.isinf(d) and np.isinf(k[1]) and k[0] == pytest.approx(0.5 * np.log(0.5))
+
+
+def test_pdf_invalid_arguments_raise():
+    import paper_2101_01160_amd as m
+    for args in ((0.0, 1.0, 0.0, 0.1, 10), (1.0, -1.0, 0.0, 0.1, 10), (1.0, 1.0, 0.0, 0.0, 10),
+                 (1.0, 1.0, 0.0, 0.1, 0), (1.0, 1.0, 0.0, 0.1, 4095), (1.0, 1.0, np.inf, 0.1, 10)):
+        with pytest.raises(m.MDLGError):
+            m.mdlg_pdf_bins(*args)
+    with pytest.raises(m.MDLGError):
+        m.mdlg_pdf_measured(np.zeros((2, 5), np.int64))
+    with pytest.raises(m.MDLGError):
+        m.mdlg_pdf_measured(np.array([1, -1, 3]))
+    with pytest.raises(m.MDLGError):
+        m.mdlg_kl_divergence([0.5, np.nan], [0.5, 0.5])
+    with pytest.raises(m.MDLGError):
+        m.mdlg_kl_divergence([0.5, 0.5], [-0.5, 1.5])
