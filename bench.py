@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline-steps", type=int, default=500,
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
-    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision", "surrogate"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision", "surrogate", "paper"),
                     help="single: the 1M box; batched: 256 uneven replicas in one launch per step; "
                          "precision: FP32 pair forces against FP64 on the 4M box")
     ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
@@ -62,6 +62,11 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
     ap.add_argument("--train-batch", type=int, default=4096, help="surrogate: minibatch")
     ap.add_argument("--groups", type=int, default=4, help="surrogate: replica groups (80 replicas each)")
+    ap.add_argument("--paper-replicas", type=int, default=4, help="paper: independent systems of 99,856 particles")
+    ap.add_argument("--events", type=int, default=20, help="paper: coarse-graining events per Table 1 row")
+    ap.add_argument("--equil", type=int, default=100000, help="paper: MD steps discarded before the sweep")
+    ap.add_argument("--rows", default="", help="paper: comma-separated Table 1 rows (0-11); default all")
+    ap.add_argument("--pdf-out", default="", help="paper: write the binned displacement PDFs and K(X_i) here (JSON)")
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch first (lj_md_autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (bandwidth and counter calibration)")
@@ -150,6 +155,9 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "paper":
+        bench_paper(args)
         return
     import torch
 
@@ -476,6 +484,165 @@ def bench_surrogate(args):
                  "surrogate_seconds_per_feq": sec_nn_per_sample,
                  "speedup": sec_md_per_sample / sec_nn_per_sample,
                  "equivalent_particle_steps_per_s": steps_per_sample * rate}}), flush=True)
+
+
+# Table 1: coarse-grained time step dt_cg (tau), lattice spacing dx (sigma), lattice points lx, MD output
+# frequency (MD steps of 1e-4 tau per coarse step).  The 5.5 / 180 row is taken as printed; the lattice
+# always has lx cells over L, so its spacing is L / lx.
+TABLE1 = [(0.3911, 4.0, 250, 3911), (0.5000, 5.0, 200, 5000), (0.5626, 5.5, 180, 5626),
+          (0.6927, 20.0 / 3.0, 150, 6927), (0.9009, 25.0 / 3.0, 120, 9009), (1.1261, 10.0, 100, 11261),
+          (1.4994, 12.5, 80, 14994), (1.6342, 40.0 / 3.0, 75, 16342), (2.0338, 15.625, 64, 20338),
+          (2.9280, 20.0, 50, 29280), (4.1821, 25.0, 40, 41821), (6.1751, 31.25, 32, 61751)]
+PAPER_N, PAPER_L, PAPER_KT, PAPER_A2 = 99856, 1000.0, 20.0, 0.1611
+# D2Q25 sets of the Results section and the outer ring of D2Q49
+SHELLS = {"f0": [0], "f1-4": [1, 2, 3, 4], "f5-8": [5, 6, 7, 8], "f9-12": [9, 10, 11, 12],
+          "f13-20": list(range(13, 21)), "f21-24": [21, 22, 23, 24], "f25-48": list(range(25, 49))}
+
+
+def bench_paper(args):
+    """The paper's sweep at reduced length: R independent systems of N = 99,856
+    LJ particles in L = 1000 at kT = 20, equilibrated once, then each Table 1
+    row in turn (its lattice lx and coarse step) with the fused coarse-graining
+    for E events, a snapshot at every event, and the displacement histograms
+    of the row's coarse step.  Per row: a^2 (the paper fixes ~0.1611 by its
+    choice of dt_cg), lambda_2, measured f_eq against the single Gaussian and
+    the WSG per D2Q25 set, and the KL divergences of the binned displacement
+    PDF (Fig. 2)."""
+    import torch
+
+    import mdlg_inputs as mi
+    import paper_2101_01160_amd as m
+
+    log = lambda s_: print("# " + s_, file=sys.stderr, flush=True)
+    R, E, N, L, kT = args.paper_replicas, args.events, PAPER_N, PAPER_L, PAPER_KT
+    rows = [int(r) for r in args.rows.split(",")] if args.rows else list(range(len(TABLE1)))
+    phi = N * math.pi / (4.0 * L * L)
+    pos, vel = [], []
+    for r in range(R):
+        rng = np.random.Generator(np.random.PCG64(args.seed + r))
+        pos.append(mi.jittered_grid(N, L, rng))
+        vel.append(mi.maxwell_velocities(N, kT, rng))
+    ntot = N * R
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    params = [m.lj_params(N, L, force_bits=args.force_bits) for _ in range(R)]
+    sysm = m.LJSystem(torch.from_numpy(np.concatenate(pos)).to(dev), torch.from_numpy(np.concatenate(vel)).to(dev),
+                      params=params)
+    info = sysm.info()
+    K = info["rebuild_every"]
+    offsets = np.arange(R + 1, dtype=np.int64) * N
+    # equilibration; its first part runs as timed graphs and gives the kernel times
+    units = max(3, math.ceil(min(args.equil, 40000) / K))
+    kms, kcnt = sysm.step_timed(units)
+    rest = max(0, args.equil - units * K)
+    if rest:
+        sysm.step(rest)
+    torch.cuda.synchronize()
+    sysm.check()
+    log(f"equilibrated {units * K + rest} MD steps; {R} x {N} particles, rebuild_every={K}")
+    n_bin = 97                 # bins of dx / 8 over +-6 dx
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    md_steps = 0
+    hist_ms = 0.0
+    raw = []
+    e0.record()
+    for ri in rows:
+        dt_cg, dx_print, lx, freq = TABLE1[ri]
+        dxl = L / lx
+        acc = sysm.attach_cg(lx, freq)
+        sp = torch.empty((E + 1, ntot, 2), dtype=torch.float64, device=dev)
+        si = torch.empty((E + 1, ntot, 2), dtype=torch.int32, device=dev)
+        m.lj_md_get_state(sysm.handle, sp[0], None, si[0])
+        for e in range(E):
+            sysm.step(freq)
+            m.lj_md_get_state(sysm.handle, sp[e + 1], None, si[e + 1])
+        md_steps += E * freq
+        hist = torch.zeros((R, 1, 2, n_bin + 2), dtype=torch.int64, device=dev)
+        h0 = torch.cuda.Event(enable_timing=True)
+        h1 = torch.cuda.Event(enable_timing=True)
+        h0.record()
+        m.mdlg_displacement_hist(offsets, [L] * R, sp, si, [1], [dxl / 8.0], n_bin, hist)
+        h1.record()
+        events = acc.events
+        counts = acc.counts.cpu().numpy()
+        moments = acc.moments.cpu().numpy()
+        sysm.detach_cg()
+        h1.synchronize()
+        hist_ms += h0.elapsed_time(h1)
+        raw.append((ri, dxl, events, counts, moments, hist.cpu().numpy()))
+        del sp, si
+        log(f"row {ri}: dt_cg={dt_cg} lx={lx} freq={freq}: {events} events")
+    e1.record()
+    torch.cuda.synchronize()
+    sysm.check()
+    ms = e0.elapsed_time(e1)
+    sysm.close()
+    value = ntot * md_steps / (ms * 1e-3)
+
+    out_rows, pdfs = [], []
+    for ri, dxl, events, counts, moments, hist in raw:
+        dt_cg, dx_print, lx, freq = TABLE1[ri]
+        c = counts.sum(axis=0)
+        g, ovf = m.mdlg_feq_measured(c, ntot, events, symmetrize=True)
+        mu2, mu4, a2 = m.mdlg_moments(moments.sum(axis=0), dxl)
+        lam, r = m.mdlg_lambda_from_moments(mu2, mu4, 2)
+        gG, gW = m.mdlg_feq_gauss(a2), m.mdlg_feq_wsg(a2, lam)
+        shells = {}
+        for name, idx in SHELLS.items():
+            cnt = float(c[idx].sum())
+            gm, gg, gw = float(g[idx].mean()), float(gG[idx].mean()), float(gW[idx].mean())
+            shells[name] = {"meas": gm, "G": gg, "WSG": gw, "meas/G-1": gm / gg - 1.0, "meas/WSG-1": gm / gw - 1.0,
+                            "poisson_se": 1.0 / math.sqrt(cnt) if cnt > 0 else None}
+        # the a^2 of each replica on its own: spread between independent systems
+        a2_rep = [m.mdlg_moments(moments[k], dxl)[2] for k in range(R)]
+        h = dxl / 8.0
+        p_md = m.mdlg_pdf_measured(hist)
+        p_g, p_w = m.mdlg_pdf_bins(mu2, lam, 0.0, h, n_bin)
+        k_g, d_g = m.mdlg_kl_divergence(p_md, p_g)
+        k_w, d_w = m.mdlg_kl_divergence(p_md, p_w)
+        _, d_wg = m.mdlg_kl_divergence(p_w, p_g)
+        samples = int(hist.sum())
+        out_rows.append({"row": ri, "dt_cg": dt_cg, "lx": lx, "dx": dxl, "freq": freq, "events": int(events),
+                         "a2": a2, "a2_replica_sd": float(np.std(a2_rep, ddof=1)) if R > 1 else None,
+                         "a2_paper": PAPER_A2, "r": r, "lambda2": lam, "overflow": ovf,
+                         "max_abs_meas_minus_G": float(np.max(np.abs(g - gG))),
+                         "max_abs_meas_minus_WSG": float(np.max(np.abs(g - gW))), "shells": shells,
+                         "kl": {"MD||G": d_g, "MD||WSG": d_w, "WSG||G": d_wg, "samples": samples,
+                                "finite_sample_bias": (n_bin + 1) / (2.0 * samples)}})
+        pdfs.append({"row": ri, "dt_cg": dt_cg, "h": h, "n_bin": n_bin, "P_MD": p_md.tolist(), "P_G": p_g.tolist(),
+                     "P_WSG": p_w.tolist(), "K_MD_G": k_g.tolist(), "K_MD_WSG": k_w.tolist()})
+    if args.pdf_out:
+        with open(args.pdf_out, "w") as f:
+            json.dump(pdfs, f)
+    t_step, t_cg, t_rebuild = (float(x) for x in kms)
+    spl = int(info.get("steps_per_launch", 1)) or 1
+    launch_ms = spl * t_step
+    launch_bytes = spl * STEP_BYTES * ntot
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    line = {
+        "metric": "MD particle-steps/s, paper regime (Table 1 sweep, fused MDLG coarse-graining)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": md_steps, "warmup": units * K + rest,
+        "ms_per_step": ms / md_steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces",
+        "data": "synthetic (jittered-grid positions, Maxwellian velocities, seeds %d..%d)" % (args.seed,
+                                                                                         args.seed + R - 1),
+        "config": {"workload": f"{R} x 2D LJ gas N={N}, L={L}, phi={phi:.6f}, kT={kT}, dt=1e-4; "
+                               f"{args.equil} equilibration steps; Table 1 rows {rows}, {E} events each",
+                   "replicas": R, "events_per_row": E, "equil_steps": args.equil},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "MD step kernel" + (", two ordinary steps per launch" if spl == 2 else ""),
+                     "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl},
+        "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
+                      "launches": [int(x) for x in kcnt], "displacement_hist_total": hist_ms},
+        "rows": out_rows,
+    }
+    if args.cpu_baseline_steps > 0:
+        log("cpu baseline (oracle) ...")
+        steps = 3 * args.cpu_baseline_steps   # ~15 s of one host core at this size
+        line["cpu_baseline"] = cpu_baseline(N, phi, kT, 250, 50, args.seed, steps)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -1838,9 +1838,21 @@ hipError_t eager_step(lj_md* md, hipStream_t st) {
     return hipSuccess;
 }
 
+// What distinguishes the kernel sequence of a unit (rebuild + K steps) starting
+// now: the offsets of its coarse-graining events.  With s_cg <= K they follow
+// from cg_t mod s_cg; with s_cg > K a unit holds at most one event, after
+// to_event steps (1 .. K), or none (0).  -1 without coarse-graining.
+int unit_phase(const lj_md* md) {
+    if (!md->cg_on) return -1;
+    const long long r = md->cg_t % md->s_cg;
+    if (md->s_cg <= md->K) return (int)r;
+    const long long to_event = md->s_cg - r;
+    return to_event <= md->K ? (int)to_event : 0;
+}
+
 // rebuild + K steps, replayed from a captured graph.
 mdlg_status graph_unit(lj_md* md, hipStream_t st) {
-    GraphKey key{md->K, md->cg_on ? (int)(md->cg_t % md->s_cg) : -1, md->ppar, md->opar, md->vpar};
+    GraphKey key{md->K, unit_phase(md), md->ppar, md->opar, md->vpar};
     auto it = md->graphs.find(key);
     if (it == md->graphs.end()) {
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
@@ -1925,12 +1937,16 @@ mdlg_status sync_check(lj_md* md, hipStream_t st) {
     return MDLG_OK;
 }
 
+// Rebuild interval with coarse-graining attached: a multiple of s_cg when K >= s_cg
+// (every unit then holds the same events), else the largest divisor of s_cg in
+// [K/2, K] (a unit then ends with an event or holds none), else K itself: a unit holds at
+// most one event, at an offset that varies from unit to unit (see unit_phase).
 int aligned_K(int K, int s_cg) {
     if (s_cg <= 0) return K;
     if (K >= s_cg) return s_cg * (K / s_cg);
-    for (int d = K; d >= 1; --d)
+    for (int d = K; d >= (K + 1) / 2; --d)
         if (s_cg % d == 0) return d;
-    return 1;
+    return K;
 }
 
 mdlg_status destroy_on_fail(lj_md* md, mdlg_status st) {
@@ -2285,7 +2301,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     std::vector<UnitRec> order;
     mdlg_status status = MDLG_OK;
     for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
-        const int phase = md->cg_on ? (int)(md->cg_t % md->s_cg) : -1;
+        const int phase = unit_phase(md);
         const auto key = std::make_tuple(K, md->ppar, md->opar, md->vpar, phase);
         auto it = cache.find(key);
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;

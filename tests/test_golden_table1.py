@@ -41,3 +41,15 @@ def test_coarse_time_grows_with_lattice_spacing():
     # the coarse time step scales faster than linearly with dx over the table
     slope = np.polyfit(np.log(r[:, 1]), np.log(r[:, 0]), 1)[0]
     assert 1.0 < slope < 2.0
+
+
+def test_benchmark_sweep_uses_the_table():
+    """The paper-regime benchmark runs exactly these rows."""
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import bench
+    r = rows()
+    assert len(bench.TABLE1) == 12
+    for (dt_cg, dx, lx, freq), ref in zip(bench.TABLE1, r):
+        assert (dt_cg, lx, freq) == (ref[0], int(ref[2]), int(ref[3]))
+        assert dx == pytest.approx(ref[1], rel=1e-15)

@@ -155,6 +155,31 @@ def test_fused_coarse_graining_matches_oracle(u, kernel):
     sysm.close()
 
 
+def test_coarse_step_without_divisor_near_rebuild_interval():
+    """A prime coarse step (97 MD steps) keeps the rebuild interval; events then
+    fall at a different offset of each graph unit.  Steps are taken one event
+    at a time (graph units plus eager steps) and then five events in one call."""
+    import torch
+    n, lx, s_cg = 512, 32, 97
+    pos0, vel0, L = mi.initial_state(n, 0.0784, 20.0, 0)
+    sysm = gpu_system(pos0, vel0, L)
+    K0 = sysm.info()["rebuild_every"]
+    acc = sysm.attach_cg(lx, s_cg)
+    K = sysm.info()["rebuild_every"]
+    print(f"rebuild_every {K0} -> {K} with s_cg={s_cg}", flush=True)
+    assert K == (K0 if K0 < s_cg else s_cg * (K0 // s_cg))
+    for _ in range(3):
+        sysm.step(s_cg)
+    sysm.step(5 * s_cg)
+    torch.cuda.synchronize()
+    sysm.check()
+    assert acc.events == 8
+    oacc = omd.CGAccum(lx)
+    omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, 8 * s_cg, cg=oacc, s_cg=s_cg)
+    assert np.array_equal(_np(acc.counts)[0], oacc.counts)
+    sysm.close()
+
+
 @pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_batched_replicas_equal_single_runs(kernel):
     import torch
