@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--groups", type=int, default=4, help="surrogate: replica groups (80 replicas each)")
     ap.add_argument("--paper-replicas", type=int, default=4, help="paper: independent systems of 99,856 particles")
     ap.add_argument("--events", type=int, default=20, help="paper: coarse-graining events per Table 1 row")
-    ap.add_argument("--equil", type=int, default=100000, help="paper: MD steps discarded before the sweep")
+    ap.add_argument("--equil", type=int, default=1000000, help="paper: MD steps discarded before the sweep")
     ap.add_argument("--rows", default="", help="paper: comma-separated Table 1 rows (0-11); default all")
     ap.add_argument("--pdf-out", default="", help="paper: write the binned displacement PDFs and K(X_i) here (JSON)")
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch first (lj_md_autotune)")
