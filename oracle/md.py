@@ -57,6 +57,9 @@ def _load():
     lib.orc_coarse_grain_literal.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, _i32p,
                                              C.c_int64, _dp, C.c_int64, _dp, C.c_int64, _i64p,
                                              C.c_void_p]
+    lib.orc_neq_mdlg.argtypes = [C.c_int32, C.c_double, _i32p, C.c_int32, _i64p, C.c_int32, C.c_int64, _dp, _i64p,
+                                 _i32p, _i64p, C.c_void_p]
+    lib.orc_neq_mdlg.restype = C.c_int
     lib.orc_displacement_hist.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_int32, _dp, C.c_void_p, _dp,
                                           C.c_void_p, _i64p]
     lib.orc_md_run.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
@@ -211,3 +214,21 @@ def displacement_hist_series(offsets, box_l, pos, img, lags, h, n_bin):
                 displacement_hist(box_l[r], h[s], n_bin, pos[p - lag, a:b], pos[p, a:b], img[p - lag, a:b],
                                   img[p, a:b], hist=out[r, s])
     return out
+
+
+def neq_mdlg(lx, L, offsets, pos, img, xi=True):
+    """Ensemble sums over replica trajectories pos/img [P, n_tot, 2] (see orc_neq_mdlg).
+    Returns (f_sum [P-1, 49, lx, lx] int32, ovf [P-1] int64, xi_sum [P-2, 49, lx, lx] int32 or None)."""
+    lib = _load()
+    pos = _f64(pos)
+    img = _i64(img)
+    P, n_tot = pos.shape[0], pos.shape[1]
+    off = _i64(offsets)
+    f_sum = np.zeros((P - 1, 49, lx, lx), dtype=np.int32)
+    ovf = np.zeros(P - 1, dtype=np.int64)
+    xi_sum = np.zeros((max(P - 2, 0), 49, lx, lx), dtype=np.int32) if xi else None
+    rc = lib.orc_neq_mdlg(int(lx), float(L), lattice.d2q49(), len(off) - 1, off, P, n_tot, pos, img, f_sum, ovf,
+                          _ptr(xi_sum) if xi and P > 2 else None)
+    if rc != 0:
+        raise MemoryError("orc_neq_mdlg")
+    return f_sum, ovf, xi_sum

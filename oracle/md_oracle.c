@@ -20,6 +20,10 @@
  *    "Molecular dynamics lattice gas method" section: particle j adds one to
  *    n_i(x, t) when it sits in lattice cell x at time t and sat in cell x - v_i
  *    at time t - dt_cg.
+ *  - Non-equilibrium MDLG: the lattice gas evolution Eq.(mdlg_evolution)
+ *    defines the collision operator Xi_i = n_i(x + v_i, t + dt) - n_i(x, t);
+ *    the MDLB quantities f_i = <n_i> and Omega_i = <Xi_i> are averages over
+ *    an ensemble of trajectories ("Molecular dynamics lattice gas method").
  *  - Displacement histogram: the binned one-particle displacement PDF
  *    P^MD(X_i) that the displacement-PDF figure (Fig. 2) sets beside the
  *    single-Gaussian Eq.(gaussian_df) and the Poisson WSG Eq.(poisson_v2).
@@ -319,6 +323,71 @@ void orc_coarse_grain_literal(int32_t lx, double L, double ux, double uy, const 
         }
     }
     counts[NQ] += n - total;
+}
+
+/* --------------------------------------------- non-equilibrium MDLG --- */
+
+/* Ensemble sums of the occupation numbers and of the lattice gas collision
+ * operator over n_rep replica trajectories.  Replica r owns particles
+ * offsets[r] .. offsets[r+1]-1 of the stacked snapshots pos [n_snap][n_tot][2]
+ * and img [n_snap][n_tot][2]; every replica has box side L and an lx x lx
+ * lattice at rest.  Event p (1 <= p < n_snap) is the coarse step from
+ * snapshot p-1 to p.  Outputs (overwritten):
+ *   f_sum [n_snap-1][49][lx][lx]: sum over r of n_i^r(x, t_p)
+ *   ovf   [n_snap-1]:            particles of event p whose lattice
+ *                                displacement is outside D2Q49
+ *   xi_sum [n_snap-2][49][lx][lx] (NULL to skip): sum over r of
+ *         Xi_i^r(x, t_p) = n_i^r(x + v_i, t_{p+1}) - n_i^r(x, t_p), x + v_i
+ *         taken on the periodic lattice, for 1 <= p < n_snap - 1.
+ * Each replica's n_i comes from the binned coarse-graining above and its
+ * Xi_i from the definition, before anything is summed over replicas. */
+int orc_neq_mdlg(int32_t lx, double L, const int32_t* vtab, int32_t n_rep, const int64_t* offsets,
+                 int32_t n_snap, int64_t n_tot, const double* pos, const int64_t* img, int32_t* f_sum,
+                 int64_t* ovf, int32_t* xi_sum) {
+    int64_t lx2 = (int64_t)lx * lx;
+    int64_t per = NQ * lx2;
+    int32_t* prev = (int32_t*)calloc((size_t)per, sizeof(int32_t));
+    int32_t* cur = (int32_t*)calloc((size_t)per, sizeof(int32_t));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return -1;
+    }
+    memset(f_sum, 0, sizeof(int32_t) * (size_t)(n_snap - 1) * (size_t)per);
+    memset(ovf, 0, sizeof(int64_t) * (size_t)(n_snap - 1));
+    if (xi_sum && n_snap > 2) memset(xi_sum, 0, sizeof(int32_t) * (size_t)(n_snap - 2) * (size_t)per);
+    for (int32_t r = 0; r < n_rep; ++r) {
+        int64_t a = offsets[r], n = offsets[r + 1] - offsets[r];
+        if (n == 0) continue;
+        for (int32_t p = 1; p < n_snap; ++p) {
+            int64_t counts[NQ + 1];
+            memset(counts, 0, sizeof(counts));
+            const double* xp = pos + 2 * ((int64_t)(p - 1) * n_tot + a);
+            const double* xc = pos + 2 * ((int64_t)p * n_tot + a);
+            const int64_t* ip = img + 2 * ((int64_t)(p - 1) * n_tot + a);
+            const int64_t* ic = img + 2 * ((int64_t)p * n_tot + a);
+            orc_coarse_grain_shift(lx, L, 0.0, 0.0, 0.0, 0.0, vtab, n, xp, ip, xc, ic, counts, cur, NULL, NULL);
+            ovf[p - 1] += counts[NQ];
+            int32_t* f = f_sum + (int64_t)(p - 1) * per;
+            for (int64_t k = 0; k < per; ++k) f[k] += cur[k];
+            if (xi_sum && p >= 2) {
+                /* event p-1 is t, event p is t + dt */
+                int32_t* xi = xi_sum + (int64_t)(p - 2) * per;
+                for (int32_t i = 0; i < NQ; ++i)
+                    for (int64_t y = 0; y < lx; ++y)
+                        for (int64_t x = 0; x < lx; ++x) {
+                            int64_t xs = pmod(x + vtab[2 * i], lx), ys = pmod(y + vtab[2 * i + 1], lx);
+                            xi[i * lx2 + y * lx + x] += cur[i * lx2 + ys * lx + xs] - prev[i * lx2 + y * lx + x];
+                        }
+            }
+            int32_t* t = prev;
+            prev = cur;
+            cur = t;
+        }
+    }
+    free(prev);
+    free(cur);
+    return 0;
 }
 
 /* ------------------------------------------------ displacement PDF --- */
