@@ -308,6 +308,36 @@ mdlg_status mdlg_feq_gauss(double a2, const double* u, double* g_out);
 mdlg_status mdlg_feq_wsg(double a2, double lambda, const double* u, double* g_out);
 
 /* ------------------------------------------------------------------------ */
+/* Non-equilibrium MDLG of a replica ensemble                                */
+/* ------------------------------------------------------------------------ */
+
+/* Ensemble sums of the occupation numbers (Eq.(n_i)) at every coarse step of
+ * stored trajectories and of the lattice gas collision operator defined with
+ * Eq.(mdlg_evolution), Xi_i(x, t) = n_i(x + v_i, t + dt) - n_i(x, t).  Divided
+ * by the ensemble size they are the MDLB distribution f_i = <n_i>_neq and
+ * collision operator Omega_i = <Xi_i>_neq of the "Molecular dynamics lattice
+ * gas method" section.  The ensemble is n_total particles over any number of
+ * replicas of one system (box side box_l, an lx x lx lattice at rest,
+ * 7 <= lx <= 46340): the sums do not depend on which particle belongs to
+ * which replica.  pos (device [n_snap][n_total][2] float64, wrapped into
+ * [0, box_l)) and img (device [n_snap][n_total][2] int32 image counts) stack
+ * n_snap >= 2 snapshots one coarse step apart; event p (1 <= p < n_snap) is
+ * the step from snapshot p-1 to p, with the lattice velocity of a particle
+ * C(p) - C(p-1) of its unwrapped cells C = floor(x lx / box_l) + lx img.
+ * Outputs (device, overwritten):
+ *   f_sum    int32 [n_snap-1][49][lx][lx]: sum of n_i(x, t_p), cell (x, y) at
+ *            [i][y][x], the destination cell taken modulo lx
+ *   overflow int64 [n_snap-1]: particles of event p whose lattice
+ *            displacement is outside D2Q49 (not counted in f_sum)
+ *   xi_sum   int32 [n_snap-2][49][lx][lx] or NULL: sum of Xi_i(x, t_p) for
+ *            1 <= p < n_snap - 1, x + v_i on the periodic lattice
+ * Integer results, exact and independent of the launch.  Asynchronous on
+ * `stream`; allocates nothing. */
+mdlg_status mdlg_neq_mdlg(int64_t n_total, double box_l, int32_t lx, int32_t n_snap, const double* pos,
+                          const int32_t* img, int32_t* f_sum, int64_t* overflow, int32_t* xi_sum,
+                          void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Displacement PDFs and the KL divergence (Fig. 2)                          */
 /* ------------------------------------------------------------------------ */
 

@@ -37,6 +37,7 @@ __all__ = [
     "replica_sweep",
     "surrogate_sweep",
     "mlp_init",
+    "shear_wave_state",
 ]
 
 
@@ -138,6 +139,18 @@ def surrogate_sweep(n_rep: int, seed: int = 12345, n: int = 16384,
         lx = max(4, int(round(L / cell)))
         out.append(ReplicaSpec(n=n, phi=phi, kT=kT, seed=seed * 1000 + r, L=L, lx=lx))
     return out
+
+
+def shear_wave_state(n: int, L: float, kT: float, amp: float, seed: int, modes: int = 1):
+    """A flowing (non-equilibrium) start for the ensemble workload: jittered-grid
+    positions in a box of side L and Maxwellian velocities at kT (as
+    initial_state, same draws), plus a transverse wave
+    v_x += amp * sin(2 pi modes y / L).  Returns (pos, vel)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jittered_grid(n, L, rng)
+    vel = maxwell_velocities(n, kT, rng)
+    vel[:, 0] += amp * np.sin(2.0 * math.pi * modes * pos[:, 1] / L)
+    return pos, np.ascontiguousarray(vel)
 
 
 MLP_DIMS = (6, 256, 256, 256, 49)

@@ -29,7 +29,7 @@ __all__ = [
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
-    "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
+    "mdlg_neq_mdlg", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy", "SurrogateMLP", "MLP_NPARAMS",
 ]
@@ -225,6 +225,19 @@ def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, mome
         int(uu.shape[0]), uu.ctypes.data_as(C.c_void_p), None if lo is None else lo.ctypes.data_as(C.c_void_p),
         _dev(counts, torch.int64, (n_rep, lg.size, uu.shape[0], 50), "counts"),
         _dev(moments, torch.float64, (n_rep, lg.size, 5), "moments"), _stream(stream)))
+
+
+def mdlg_neq_mdlg(box_l, lx, pos, img, f_sum, overflow, xi_sum=None, stream=None):
+    """pos: torch float64 [P, n_total, 2], img: torch int32 [P, n_total, 2] on the GPU (an ensemble of
+    replicas of one system, snapshots one coarse step apart); outputs (overwritten): f_sum int32
+    [P-1, 49, lx, lx], overflow int64 [P-1], xi_sum int32 [P-2, 49, lx, lx] or None."""
+    torch = _torch()
+    P, n = int(pos.shape[0]), int(pos.shape[1])
+    lx = int(lx)
+    _abi.check(_abi.lib().mdlg_neq_mdlg(
+        n, float(box_l), lx, P, _dev(pos, torch.float64, (P, n, 2), "pos"), _dev(img, torch.int32, (P, n, 2), "img"),
+        _dev(f_sum, torch.int32, (P - 1, 49, lx, lx), "f_sum"), _dev(overflow, torch.int64, (P - 1,), "overflow"),
+        _dev(xi_sum, torch.int32, (max(P - 2, 0), 49, lx, lx), "xi_sum"), _stream(stream)))
 
 
 def mdlg_displacement_hist(offsets, box_l, pos, img, lags, bin_width, n_bin, hist, stream=None):
