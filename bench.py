@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline-steps", type=int, default=500,
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
-    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision", "surrogate", "paper"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "precision", "surrogate", "paper", "neq"),
                     help="single: the 1M box; batched: 256 uneven replicas in one launch per step; "
                          "precision: FP32 pair forces against FP64 on the 4M box")
     ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--events", type=int, default=20, help="paper: coarse-graining events per Table 1 row")
     ap.add_argument("--equil", type=int, default=1000000, help="paper: MD steps discarded before the sweep")
     ap.add_argument("--rows", default="", help="paper: comma-separated Table 1 rows (0-11); default all")
+    ap.add_argument("--neq-replicas", type=int, default=256, help="neq: ensemble size")
+    ap.add_argument("--neq-events", type=int, default=100, help="neq: coarse steps recorded")
     ap.add_argument("--pdf-out", default="", help="paper: write the binned displacement PDFs and K(X_i) here (JSON)")
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch first (lj_md_autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -158,6 +160,9 @@ def main():
         return
     if args.workload == "paper":
         bench_paper(args)
+        return
+    if args.workload == "neq":
+        bench_neq(args)
         return
     import torch
 
@@ -642,6 +647,134 @@ def bench_paper(args):
         log("cpu baseline (oracle) ...")
         steps = 3 * args.cpu_baseline_steps   # ~15 s of one host core at this size
         line["cpu_baseline"] = cpu_baseline(N, phi, kT, 250, 50, args.seed, steps)
+    print(json.dumps(line), flush=True)
+
+
+def _decay_rate(t, a, floor):
+    """Least-squares rate of exp(-g t) through the points with a > floor: (g, points used)."""
+    t = np.asarray(t, dtype=np.float64)
+    a = np.asarray(a, dtype=np.float64)
+    keep = a > floor
+    if keep.sum() < 3:
+        return float("nan"), int(keep.sum())
+    slope = np.polyfit(t[keep], np.log(a[keep]), 1)[0]
+    return float(-slope), int(keep.sum())
+
+
+def bench_neq(args):
+    """Non-equilibrium MDLG of an ensemble: R replicas of a small LJ gas (N = 998,
+    L = 100, phi = 0.0784, kT = 20) started as the same transverse wave
+    v_x = 4 sin(2 pi y / L) over independent thermal noise, a snapshot per
+    coarse step (Table 1 row 0: dt_cg = 0.3911, dx = 4, lx = 25), then the
+    ensemble sums of n_i(x, t) and of the collision operator Xi_i(x, t) on the
+    GPU.  Reports the throughput, the MDLG kernels against their rooflines,
+    the decay rate of the flow's momentum mode seen by the MDLB f_i against the
+    rate seen in the MD velocities, and the per-cell mass identity of Xi."""
+    import torch
+
+    import mdlg_inputs as mi
+    import paper_2101_01160_amd as m
+
+    log = lambda s_: print("# " + s_, file=sys.stderr, flush=True)
+    R, E = args.neq_replicas, args.neq_events
+    n, L, kT, amp, lx, s_cg = 998, 100.0, 20.0, 4.0, 25, 3911
+    dt_cg = s_cg * 1e-4
+    states = [mi.shear_wave_state(n, L, kT, amp, seed=args.seed + r) for r in range(R)]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sysm = m.LJSystem(torch.from_numpy(np.concatenate([s[0] for s in states])).to(dev),
+                      torch.from_numpy(np.concatenate([s[1] for s in states])).to(dev),
+                      params=[m.lj_params(n, L, force_bits=args.force_bits) for _ in range(R)])
+    ntot = n * R
+    info = sysm.info()
+    K = info["rebuild_every"]
+    sp = torch.empty((E + 1, ntot, 2), dtype=torch.float64, device=dev)
+    si = torch.empty((E + 1, ntot, 2), dtype=torch.int32, device=dev)
+    sv = torch.empty((E + 1, ntot, 2), dtype=torch.float64, device=dev)
+    # kernel times of the step on this ensemble (graph replays with events), then back to the start
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    m.lj_md_get_state(sysm.handle, sp[0], sv[0], si[0])
+    e0.record()
+    for e in range(E):
+        sysm.step(s_cg)
+        m.lj_md_get_state(sysm.handle, sp[e + 1], sv[e + 1], si[e + 1])
+    e1.record()
+    torch.cuda.synchronize()
+    sysm.check()
+    ms_md = e0.elapsed_time(e1)
+    kms, kcnt = sysm.step_timed(3)
+    sysm.close()
+    log(f"{R} x {n} particles, {E} coarse steps of {s_cg} MD steps in {ms_md:.1f} ms")
+    f = torch.empty((E, 49, lx, lx), dtype=torch.int32, device=dev)
+    ovf = torch.empty(E, dtype=torch.int64, device=dev)
+    xi = torch.empty((E - 1, 49, lx, lx), dtype=torch.int32, device=dev)
+    for _ in range(2):
+        m.mdlg_neq_mdlg(L, lx, sp, si, f, ovf, xi)
+    reps = 20
+    t = []
+    for with_xi in (False, True):
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(reps):
+            m.mdlg_neq_mdlg(L, lx, sp, si, f, ovf, xi if with_xi else None)
+        a1.record()
+        torch.cuda.synchronize()
+        t.append(a0.elapsed_time(a1) / reps)
+    ms_scatter, ms_xi = t[0], max(t[1] - t[0], 1e-6)
+    F = f.cpu().numpy().astype(np.int64)
+    O = ovf.cpu().numpy()
+    X = xi.cpu().numpy().astype(np.int64)
+    # per-cell identity: sum_i Xi_i(x, t) = (moves out of x that stay in D2Q49) - (moves in); globally
+    # sum_x,i Xi(t_p) = ovf(t_p) - ovf(t_{p+1})
+    glob = X.sum(axis=(1, 2, 3))
+    mass_ok = bool(np.array_equal(glob, O[:-1] - O[1:]))
+    # momentum mode of the flow: MDLB lattice momentum per row against the MD velocities
+    vt = m.mdlg_velocity_table().astype(np.int64)
+    jx = np.einsum("eiyx,i->ey", F, vt[:, 0]) / float(R * lx)          # cells per coarse step per cell
+    yc = (np.arange(lx) + 0.5) * (L / lx)
+    a_lb = 2.0 / lx * (jx * np.sin(2 * math.pi * yc / L)[None, :]).sum(axis=1)
+    P_ = sp.cpu().numpy()
+    V_ = sv.cpu().numpy()
+    a_md = 2.0 / ntot * (V_[:, :, 0] * np.sin(2 * math.pi * P_[:, :, 1] / L)).sum(axis=1)
+    t_lb = (np.arange(1, E + 1) - 0.5) * dt_cg       # each event measures the window ending at t_p
+    t_md = np.arange(E + 1) * dt_cg
+    # fit while the mode is above a tenth of its start (the thermal noise of the ensemble mean is far below)
+    g_md, used_md = _decay_rate(t_md, a_md, 0.1 * a_md[0])
+    g_lb, used_lb = _decay_rate(t_lb, a_lb, 0.1 * a_lb[0])
+    k2 = (2 * math.pi / L) ** 2
+    # roofline of the MDLG kernels: scatter reads one snapshot (24 B) and adds one 4 B counter per
+    # particle-event; the collision stencil reads two fields and writes one (12 B per element)
+    scatter_bytes = 28.0 * ntot * E
+    xi_bytes = 12.0 * (E - 1) * 49 * lx * lx
+    t_step = float(kms[0])
+    spl = int(info.get("steps_per_launch", 1)) or 1
+    launch_ms = spl * t_step
+    achieved = spl * STEP_BYTES * ntot / (launch_ms * 1e-3) / 1e9
+    value = ntot * E * s_cg / (ms_md * 1e-3)
+    line = {
+        "metric": "MD particle-steps/s, non-equilibrium MDLG ensemble (shear wave)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": E * s_cg, "warmup": 0,
+        "ms_per_step": ms_md / (E * s_cg), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 state; int32 occupation sums",
+        "data": "synthetic (jittered grid, Maxwellian + transverse wave, seeds %d..%d)" % (args.seed, args.seed + R - 1),
+        "config": {"workload": f"ensemble of {R} x 2D LJ gas N={n}, L={L}, kT={kT}, v_x += {amp} sin(2 pi y/L); "
+                               f"lattice {lx}x{lx}, coarse step {s_cg} MD steps, {E} coarse steps recorded",
+                   "replicas": R, "events": E},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "MD step kernel",
+                     "kernel_ms": launch_ms, "steps_per_launch": spl},
+        "mdlg_kernels": {
+            "scatter_and_fill_ms": ms_scatter, "scatter_gbs": scatter_bytes / (ms_scatter * 1e-3) / 1e9,
+            "xi_ms": ms_xi, "xi_gbs": xi_bytes / (ms_xi * 1e-3) / 1e9,
+            "scatter_bytes": scatter_bytes, "xi_bytes": xi_bytes},
+        "neq": {"mass_identity_exact": mass_ok, "overflow_per_event": float(O.mean()),
+                "omega_l1_over_f_l1": float(np.abs(X).sum() / max(F[:-1].sum(), 1)),
+                "momentum_mode_initial": {"md": float(a_md[0]), "mdlb": float(a_lb[0])},
+                "decay_rate_md": g_md, "decay_rate_mdlb": g_lb, "points_md": used_md, "points_mdlb": used_lb,
+                "nu_md": g_md / k2, "nu_mdlb": g_lb / k2},
+    }
     print(json.dumps(line), flush=True)
 
 
