@@ -18,6 +18,9 @@ Follows
     one-axis displacement PDFs, integrated over the bins X_k of a histogram
     (the comparison of Fig. 2).
   * Eq.(k_Xi) and Eq.(kullback_leibler): element-wise and summed KL divergence.
+  * lambda from the velocity autocorrelation function, the alternative the
+    text names beside the moment matching of Eq.(lambda_eq) (no formula is
+    given; the reading is in lambda_vacf).
 """
 from __future__ import annotations
 
@@ -233,3 +236,25 @@ def kl_divergence(R, Q):
         if r > 0:
             acc += mp.mpf(r) * mp.log(mp.mpf(r) / mp.mpf(q))
     return float(acc)
+
+
+# ------------------------------------------------------- lambda from VACF ---
+
+def lambda_vacf(t, c, dt_cg, cut=0.01):
+    """Average number of collisions in a coarse step from the velocity
+    autocorrelation C(t) (t ascending, t[0] = 0).  Reading: if collisions
+    arrive as a Poisson process of rate 1/tau and each one forgets the
+    velocity, C(t) = C(0) exp(-t / tau) and the expected count in dt_cg is
+    lambda = dt_cg / tau.  tau is taken as the integral of C(t) / C(0)
+    (trapezoid rule) up to the first sample with C <= cut C(0), or over all
+    samples if none is.  Returns (tau, lambda)."""
+    t = [mp.mpf(float(x)) for x in t]
+    c = [mp.mpf(float(x)) for x in c]
+    if len(t) < 2 or c[0] <= 0:
+        raise ValueError("need >= 2 samples and C(0) > 0")
+    tau = mp.mpf(0)
+    for k in range(1, len(t)):
+        tau += (t[k] - t[k - 1]) * (c[k] + c[k - 1]) / (2 * c[0])
+        if c[k] <= cut * c[0]:
+            break
+    return float(tau), float(mp.mpf(float(dt_cg)) / tau)

@@ -232,3 +232,20 @@ def neq_mdlg(lx, L, offsets, pos, img, xi=True):
     if rc != 0:
         raise MemoryError("orc_neq_mdlg")
     return f_sum, ovf, xi_sum
+
+
+def vacf_sums(offsets, vel, lags):
+    """Velocity autocorrelation sums of stacked velocity snapshots vel [P, n_tot, 2]:
+    out[r, s] = sum over particles j of replica r and origins p = 0 .. P-1-lag of
+    v_j(p) . v_j(p + lag), lag = lags[s], summed in FP64 (numpy pairwise order).
+    Returns [n_rep, n_lag] float64."""
+    vel = _f64(vel)
+    P = vel.shape[0]
+    offsets = [int(o) for o in offsets]
+    out = np.zeros((len(offsets) - 1, len(lags)))
+    for r in range(len(offsets) - 1):
+        a, b = offsets[r], offsets[r + 1]
+        for s, lag in enumerate(lags):
+            if b > a:
+                out[r, s] = float(np.sum(vel[:P - lag, a:b] * vel[lag:, a:b]))
+    return out
