@@ -545,6 +545,27 @@ def bench_paper(args):
     torch.cuda.synchronize()
     sysm.check()
     log(f"equilibrated {units * K + rest} MD steps; {R} x {N} particles, rebuild_every={K}")
+    # velocity autocorrelation over 6 tau (a snapshot every 100 MD steps), for lambda from the VACF
+    vstride, vsnap = 100, 601
+    vs = torch.empty((vsnap, ntot, 2), dtype=torch.float64, device=dev)
+    m.lj_md_get_state(sysm.handle, None, vs[0], None)
+    for p_ in range(1, vsnap):
+        sysm.step(vstride)
+        m.lj_md_get_state(sysm.handle, None, vs[p_], None)
+    vlags = sorted({0} | {int(round(x)) for x in np.geomspace(1, vsnap - 1, 64)})
+    csum = torch.zeros((R, len(vlags)), dtype=torch.float64, device=dev)
+    v0 = torch.cuda.Event(enable_timing=True)
+    v1 = torch.cuda.Event(enable_timing=True)
+    v0.record()
+    m.mdlg_vacf(offsets, vs, vlags, csum)
+    v1.record()
+    torch.cuda.synchronize()
+    vacf_ms = v0.elapsed_time(v1)
+    del vs
+    c_t = csum.cpu().numpy().sum(axis=0) / np.array([ntot * (vsnap - l) for l in vlags], dtype=np.float64)
+    t_t = np.array(vlags, dtype=np.float64) * vstride * 1e-4
+    tau_vacf, _ = m.mdlg_lambda_vacf(t_t, c_t, 1.0, 0.01)
+    log(f"VACF: C(0) = {c_t[0]:.3f}, tau = {tau_vacf:.4f} ({vacf_ms:.1f} ms for {len(vlags)} lags)")
     n_bin = 97                 # bins of dx / 8 over +-6 dx
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -608,9 +629,11 @@ def bench_paper(args):
         k_w, d_w = m.mdlg_kl_divergence(p_md, p_w)
         _, d_wg = m.mdlg_kl_divergence(p_w, p_g)
         samples = int(hist.sum())
+        _, lam_vacf = m.mdlg_lambda_vacf(t_t, c_t, dt_cg, 0.01)
         out_rows.append({"row": ri, "dt_cg": dt_cg, "lx": lx, "dx": dxl, "freq": freq, "events": int(events),
                          "a2": a2, "a2_replica_sd": float(np.std(a2_rep, ddof=1)) if R > 1 else None,
-                         "a2_paper": PAPER_A2, "r": r, "lambda2": lam, "overflow": ovf,
+                         "a2_paper": PAPER_A2, "r": r, "lambda2": lam, "lambda1": (1.0 / lam if lam > 0 else None),
+                         "lambda_vacf": lam_vacf, "overflow": ovf,
                          "max_abs_meas_minus_G": float(np.max(np.abs(g - gG))),
                          "max_abs_meas_minus_WSG": float(np.max(np.abs(g - gW))), "shells": shells,
                          "kl": {"MD||G": d_g, "MD||WSG": d_w, "WSG||G": d_wg, "samples": samples,
@@ -640,7 +663,9 @@ def bench_paper(args):
                      "kernel": "MD step kernel" + (", two ordinary steps per launch" if spl == 2 else ""),
                      "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl},
         "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
-                      "launches": [int(x) for x in kcnt], "displacement_hist_total": hist_ms},
+                      "launches": [int(x) for x in kcnt], "displacement_hist_total": hist_ms, "vacf": vacf_ms},
+        "vacf": {"tau": tau_vacf, "C0": float(c_t[0]), "two_kT": 2 * kT, "stride_md_steps": vstride,
+                 "snapshots": vsnap, "t": t_t[::8].tolist(), "C_over_C0": (c_t[::8] / c_t[0]).tolist()},
         "rows": out_rows,
     }
     if args.cpu_baseline_steps > 0:

@@ -338,6 +338,33 @@ mdlg_status mdlg_neq_mdlg(int64_t n_total, double box_l, int32_t lx, int32_t n_s
                           void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Velocity autocorrelation and lambda from it                               */
+/* ------------------------------------------------------------------------ */
+
+/* Velocity autocorrelation sums of stored velocity snapshots, for estimating
+ * the average number of collisions lambda of the Poisson-WSG model from the
+ * velocity autocorrelation function (the alternative to moment matching
+ * named in the section on the Poisson weighted sum of Gaussians).  Replica r
+ * owns particles offsets[r] .. offsets[r+1]-1 (host [n_rep + 1], offsets[0]
+ * = 0); vel (device [n_snap][n_tot][2] float64) stacks n_snap >= 1 snapshots
+ * at a fixed stride.  For each lag lags[s] (host [n_lag], 0 .. n_snap - 1,
+ * n_lag <= 1024) adds to c_sum (device float64 [n_rep][n_lag]) the sum over
+ * the replica's particles j and origins p = 0 .. n_snap-1-lag of
+ * v_j(p) . v_j(p + lag); the caller divides by n_r (n_snap - lag).  FP64,
+ * fixed-order reductions (bitwise reproducible).  Synchronises the stream. */
+mdlg_status mdlg_vacf(int32_t n_rep, const int64_t* offsets, int32_t n_snap, const double* vel,
+                      int32_t n_lag, const int32_t* lags, double* c_sum, void* stream);
+
+/* lambda = dt_cg / tau, the expected number of collisions in a coarse step if
+ * collisions arrive as a Poisson process of rate 1/tau that each forget the
+ * velocity (then C(t) = C(0) exp(-t / tau)).  tau is the trapezoid integral
+ * of C(t) / C(0) over the samples (t host [n] increasing, t[0] = 0; c host
+ * [n], C(0) > 0) up to and including the first one with C <= cut C(0), or
+ * over all of them.  Outputs (host, may be NULL): tau, lambda. */
+mdlg_status mdlg_lambda_vacf(int32_t n, const double* t, const double* c, double dt_cg, double cut,
+                             double* tau, double* lambda);
+
+/* ------------------------------------------------------------------------ */
 /* Displacement PDFs and the KL divergence (Fig. 2)                          */
 /* ------------------------------------------------------------------------ */
 

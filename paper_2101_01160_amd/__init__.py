@@ -29,7 +29,7 @@ __all__ = [
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
-    "mdlg_neq_mdlg", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
+    "mdlg_neq_mdlg", "mdlg_vacf", "mdlg_lambda_vacf", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy", "SurrogateMLP", "MLP_NPARAMS",
 ]
@@ -225,6 +225,31 @@ def mdlg_coarse_grain_series(offsets, box_l, lx, pos, img, lags, u, counts, mome
         int(uu.shape[0]), uu.ctypes.data_as(C.c_void_p), None if lo is None else lo.ctypes.data_as(C.c_void_p),
         _dev(counts, torch.int64, (n_rep, lg.size, uu.shape[0], 50), "counts"),
         _dev(moments, torch.float64, (n_rep, lg.size, 5), "moments"), _stream(stream)))
+
+
+def mdlg_vacf(offsets, vel, lags, c_sum, stream=None):
+    """vel: torch float64 [P, n_tot, 2] on the GPU; c_sum: torch float64 [n_rep, n_lag] on the GPU (added to)."""
+    torch = _torch()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_rep = off.size - 1
+    lg = np.ascontiguousarray(lags, dtype=np.int32).ravel()
+    P, n_tot = int(vel.shape[0]), int(vel.shape[1])
+    if n_tot != int(off[-1]):
+        raise ValueError("vel holds a different particle count than offsets")
+    _abi.check(_abi.lib().mdlg_vacf(int(n_rep), off.ctypes.data_as(C.c_void_p), P,
+                                    _dev(vel, torch.float64, (P, n_tot, 2), "vel"), int(lg.size),
+                                    lg.ctypes.data_as(C.c_void_p), _dev(c_sum, torch.float64, (n_rep, lg.size), "c_sum"),
+                                    _stream(stream)))
+
+
+def mdlg_lambda_vacf(t, c, dt_cg, cut=0.01):
+    """(tau, lambda) from sampled C(t)."""
+    tt = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    cc = _host(c, np.float64, tt.size)
+    tau, lam = C.c_double(), C.c_double()
+    _abi.check(_abi.lib().mdlg_lambda_vacf(int(tt.size), tt.ctypes.data_as(C.c_void_p), cc.ctypes.data_as(C.c_void_p),
+                                           float(dt_cg), float(cut), C.byref(tau), C.byref(lam)))
+    return tau.value, lam.value
 
 
 def mdlg_neq_mdlg(box_l, lx, pos, img, f_sum, overflow, xi_sum=None, stream=None):

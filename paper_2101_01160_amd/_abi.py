@@ -23,7 +23,7 @@ EXPORTS = [
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg",
-    "mdlg_neq_mdlg", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
+    "mdlg_neq_mdlg", "mdlg_vacf", "mdlg_lambda_vacf", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy",
 ]
@@ -127,6 +127,8 @@ def lib() -> C.CDLL:
         "mdlg_lambda_from_moments": (i32, [dbl, dbl, i32, P(dbl), P(dbl)]),
         "mdlg_feq_gauss": (i32, [dbl, vp, vp]),
         "mdlg_feq_wsg": (i32, [dbl, dbl, vp, vp]),
+        "mdlg_vacf": (i32, [i32, vp, i32, vp, i32, vp, vp, vp]),
+        "mdlg_lambda_vacf": (i32, [i32, vp, vp, dbl, dbl, P(dbl), P(dbl)]),
         "mdlg_neq_mdlg": (i32, [i64, dbl, i32, i32, vp, vp, vp, vp, vp, vp]),
         "mdlg_displacement_hist": (i32, [i32, vp, vp, i32, vp, vp, i32, vp, vp, i32, vp, vp]),
         "mdlg_pdf_bins": (i32, [dbl, dbl, dbl, dbl, i32, vp, vp]),

@@ -151,3 +151,18 @@ def test_pdf_invalid_arguments_raise():
         m.mdlg_kl_divergence([0.5, np.nan], [0.5, 0.5])
     with pytest.raises(m.MDLGError):
         m.mdlg_kl_divergence([0.5, 0.5], [-0.5, 1.5])
+
+
+def test_lambda_vacf_matches_oracle():
+    import paper_2101_01160_amd as m
+    rng = np.random.default_rng(9)
+    t = np.concatenate([[0.0], np.cumsum(rng.uniform(0.01, 0.05, 199))])
+    for c in (40.0 * np.exp(-t / 0.6) + rng.normal(0, 0.05, t.size), np.full(t.size, 2.0)):
+        c[0] = abs(c[0]) + 1.0
+        for cut in (0.01, 0.1):
+            got = m.mdlg_lambda_vacf(t, c, 0.3911, cut)
+            ref = cf.lambda_vacf(t, c, 0.3911, cut)
+            assert got == pytest.approx(ref, rel=1e-13)
+    for bad in ((t, -c, 1.0), (t[::-1].copy(), c, 1.0), (t, c, 0.0)):
+        with pytest.raises(m.MDLGError):
+            m.mdlg_lambda_vacf(*bad)
