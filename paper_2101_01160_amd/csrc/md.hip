@@ -749,18 +749,37 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
 // position loads, then the arithmetic (entries past the list are masked).
 // Without `interior` every separation goes through the minimum image, which
 // leaves separations below L/2 unchanged bit for bit.
+// Neighbour-list entries are read U rows at a time.  The list has maxnb rows,
+// a multiple of U, so rows j0 .. j0 + U - 1 exist whenever j0 < nn: they are
+// loaded without waiting for the count nn, and entries past nn are replaced
+// by 0 (a valid index) before they are used as one.
+constexpr int kListU = 4;
+
+template <typename Entry>
+__device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsigned int off, unsigned int stride,
+                                          int (&kk)[kListU]) {
+#pragma unroll
+    for (int u = 0; u < kListU; ++u) kk[u] = list[off + u * stride];
+}
+
 template <bool F32, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
-                                            double& fy) {
+                                            double& fy, const int (&first)[kListU], bool use_first) {
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
-    constexpr int U = 4;
+    constexpr int U = kListU;
     for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
         int kk[U];
+        if (use_first && j0 == 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) kk[u] = list[j0 + u < nn ? off + u * stride : off];
+            for (int u = 0; u < U; ++u) kk[u] = first[u];
+        } else {
+            list_rows(list, off, stride, kk);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) kk[u] = j0 + u < nn ? kk[u] : 0;
         double2 q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) q[u] = fetch(kk[u]);
@@ -799,6 +818,16 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
     }
     fx = F32 ? (double)bx : ax;
     fy = F32 ? (double)by : ay;
+}
+
+template <bool F32, typename Entry, typename Fetch>
+__device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
+                                            unsigned int stride, Fetch fetch, bool interior, double L, double invL,
+                                            double rc2, double eps24, float rc2f, float eps24f, double& fx,
+                                            double& fy) {
+    const int none[kListU] = {0, 0, 0, 0};
+    nlist_force<F32>(p, nn, list, off, stride, fetch, interior, L, invL, rc2, eps24, rc2f, eps24f, fx, fy, none,
+                     false);
 }
 
 // Velocity-Verlet update with the force at the current position: complete
@@ -1092,11 +1121,20 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     const double2* __restrict__ pin = a.pin;
     const int nr = R.n, slot0 = R.slot0;
     const unsigned int S = (unsigned int)a.nslots;
+    // the thread's first owned particle: its slot, count and first list rows for
+    // the second step, loaded before the barrier
+    int s_first = 0, nn_first = 0;
+    int pre[kListU] = {0, 0, 0, 0};
     for (int q = threadIdx.x; q < tot; q += BS) {
         const int s = list[q];
         const double2 p = pin[s];
         double2 v = a.vel[s];
         const int nn = a.nbc[s];
+        if (q == (int)threadIdx.x && q < own) {
+            s_first = s;
+            nn_first = nn;
+            list_rows(a.nbl2, (unsigned int)s, S, pre);
+        }
         const int srel = s - slot0;
         auto fetch = [&](int k) {
             int kr = srel + k;
@@ -1116,14 +1154,15 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     }
     __syncthreads();
     for (int q = threadIdx.x; q < own; q += BS) {
-        const int s = list[q];
+        const bool firstq = q == (int)threadIdx.x;
+        const int s = firstq ? s_first : list[q];
         const double2 p = xs[q];
         double2 v = vs[q];
-        const int nn = a.nbc[s];
+        const int nn = firstq ? nn_first : a.nbc[s];
         auto fetch = [&](int k) { return xs[k]; };
         double fx, fy;
         nlist_force<F32>(p, nn, a.nbl2, (unsigned int)s, S, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
-                         R.eps24f, fx, fy);
+                         R.eps24f, fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
         const char2 w1 = wr[q];
@@ -2089,6 +2128,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             mean_max = std::max(mean_max, 3.14159265358979 * d.w * d.w * (double)d.n / (d.L * d.L));
         }
         md->maxnb = std::min(248, ((int)std::ceil(2.0 * mean_max + 16.0) + 7) / 8 * 8);
+        static_assert(248 % kListU == 0, "list rows are read kListU at a time");
         for (int r = 0; r < n_rep; ++r) {
             // list entries are 16-bit slot offsets: a neighbour lies within about
             // three cell rows of a particle in cell order
