@@ -26,6 +26,12 @@ constexpr int kMaxSplit = 32;
 // fixed input scaling: phi / 0.4, kT / 20, (dt_cg/dx) * 100, |u| / 0.2, cos, sin
 __constant__ float c_scale[kIn] = {2.5f, 0.05f, 100.0f, 5.0f, 1.0f, 1.0f};
 
+// Logistic function and SiLU in fp32, the reciprocal from the hardware
+// estimate (about one ulp); every consumer rounds the result to bf16 (8
+// significant bits) first.  Training and inference share them.
+__device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
+
 // Epilogues: STORE C; BIAS_SILU C = z = acc + bias and H = silu(z); BIAS C =
 // acc + bias; SILU_BWD H = acc * silu'(Z) (the backward pass through an
 // activation).
@@ -158,13 +164,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 float z = acc[i][j][r];
                 if (EPI == EPI_SILU_BWD) {
                     const float zz = g.Z[m * g.ldh + n];
-                    const float sg = 1.0f / (1.0f + __expf(-zz));
+                    const float sg = sigmoid_f(zz);
                     g.H[m * g.ldh + n] = (bf16)(z * sg * (1.0f + zz * (1.0f - sg)));
                     continue;
                 }
                 if (EPI != EPI_STORE) z += g.bias[n];
                 C[m * g.ldc + n] = z;
-                if (EPI == EPI_BIAS_SILU) g.H[m * g.ldh + n] = (bf16)(z / (1.0f + __expf(-z)));
+                if (EPI == EPI_BIAS_SILU) g.H[m * g.ldh + n] = (bf16)silu_f(z);
             }
 }
 
@@ -313,12 +319,14 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 (&acc)[4][4], const 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float z = acc[i][j][r] + bj;
-                H[16 * i + 4 * (lane >> 4) + r][col] = (bf16)(z / (1.0f + __expf(-z)));
+                H[16 * i + 4 * (lane >> 4) + r][col] = (bf16)silu_f(z);
             }
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x, int B, const bf16* __restrict__ wt,
+// At most 128 registers per lane: four waves per SIMD, so that one block's
+// epilogue overlaps another's products.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_infer(const float* __restrict__ x, int B, const bf16* __restrict__ wt,
                                                    const float* __restrict__ w, float* __restrict__ g) {
     __shared__ __attribute__((aligned(16))) bf16 H[kFB][kHLD];
     __shared__ __attribute__((aligned(16))) bf16 X[kFB][40];
@@ -353,10 +361,15 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x, 
             for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
         }
     }
+    // layers 2 and 3: k = 256; the first weight fragments of a layer are loaded
+    // before the previous layer's epilogue
+    const long wo[2] = {kW2, kW3}, bo[2] = {kB2, kB3};
+    bf16x8 b[4], bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(wt + kW2 + (64 * wv + lr) * kHid + lk + 16 * j * kHid);
     hidden_epilogue(acc, w + kB1, H, wv, lane);
     __syncthreads();
-    // layers 2 and 3: k = 256
-    const long wo[2] = {kW2, kW3}, bo[2] = {kB2, kB3};
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
 #pragma unroll
@@ -365,10 +378,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x, 
             for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         const bf16* __restrict__ W = wt + wo[l] + (64 * wv + lr) * kHid + lk;
         // the weight fragments of the next k step are in flight during this one's products
-        bf16x8 b[4], bn[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kHid);
-#pragma unroll 1
+#pragma unroll 2
         for (int ks = 0; ks < kHid / 32; ++ks) {
             if (ks + 1 < kHid / 32) {
 #pragma unroll
@@ -387,6 +397,11 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x, 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) b[j] = bn[j];
             }
+        }
+        if (l == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(wt + kW3 + (64 * wv + lr) * kHid + lk + 16 * j * kHid);
         }
         __syncthreads();  // every wave has read this layer's input
         hidden_epilogue(acc, w + bo[l], H, wv, lane);
