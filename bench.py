@@ -58,6 +58,7 @@ def parse():
                     help="single: the 1M box; batched: 256 uneven replicas in one launch per step; "
                          "precision: FP32 pair forces against FP64 on the 4M box")
     ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
+    ap.add_argument("--precision-steps", type=int, default=10000, help="precision: MD steps per run")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
     ap.add_argument("--train-batch", type=int, default=4096, help="surrogate: minibatch")
@@ -271,7 +272,7 @@ def bench_precision(args):
 
     n = 1 << 22 if args.n == (1 << 20) else args.n
     lx = 2048 if args.lx == 1024 else args.lx
-    s_cg, md_steps = args.s_cg, args.steps * args.s_cg
+    s_cg, md_steps = args.s_cg, args.precision_steps
     dev = torch.device("cuda:0")
     rows = []
     for seed in range(args.seeds):
@@ -308,7 +309,7 @@ def bench_precision(args):
         "metric": "FP32 pair forces vs FP64: particle-steps/s and f_eq difference", "unit": "particle-steps/s",
         "value": float(np.mean([r[32]["rate"] for r in rows])),
         "fp64_value": float(np.mean([r[64]["rate"] for r in rows])),
-        "n_gpus": 1, "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+        "n_gpus": 1, "steps": md_steps, "warmup": 0, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 state, f32 pair forces", "data": "synthetic",
         "config": {"workload": f"2D LJ gas N={n}, phi={args.phi}, kT={args.kT}, {md_steps} MD steps, lattice "
                                f"{lx}x{lx}, coarse step {s_cg}, seeds 0..{args.seeds - 1}"},
