@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--step-kernel", type=int, default=0)
     ap.add_argument("--gather-batch", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--coarse-sweep", type=int, default=1, help="also time coarse steps of 10 and 200 MD steps")
     ap.add_argument("--cpu-baseline-steps", type=int, default=500,
                     help="MD steps of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--workload", default="single", choices=("single", "batched", "precision", "surrogate", "paper", "neq"),
@@ -219,6 +220,27 @@ def main():
     lam, r = m.mdlg_lambda_from_moments(mu2, mu4, 2)
     gG = m.mdlg_feq_gauss(a2)
     gW = m.mdlg_feq_wsg(a2, lam)
+    # the other coarse steps of the workload (10 and 200 MD steps): same system, lattice re-attached
+    other = {}
+    for sc in (10, 200):
+        if sc == s_cg or not args.coarse_sweep:
+            continue
+        sysm.detach_cg()
+        sysm.attach_cg(lx, sc)
+        Ks = sysm.info()["rebuild_every"]
+        sysm.step_timed(max(4, math.ceil(2 * sc / Ks)))
+        u = max(3, math.ceil(args.steps * s_cg / Ks))
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record()
+        km, _ = sysm.step_timed(u)
+        f1.record()
+        torch.cuda.synchronize()
+        sysm.check()
+        ms_s = f0.elapsed_time(f1)
+        other[str(sc)] = {"particle_steps_per_s": n * u * Ks / (ms_s * 1e-3), "us_per_md_step": ms_s * 1e3 / (u * Ks),
+                          "rebuild_every": Ks, "kernel_ms": {"step": float(km[0]), "step_with_cg_event": float(km[1]),
+                                                             "rebuild": float(km[2])}}
     sysm.close()
 
     line = {
@@ -248,6 +270,7 @@ def main():
         "us_per_md_step": ms * 1e3 / md_steps,
         "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
                       "launches": [int(x) for x in kcnt]},
+        "other_coarse_steps": other,
         "cell_updates_per_s": (lx * lx) / (cg_extra_ms * 1e-3),
         "particles_binned_per_s": n / (cg_extra_ms * 1e-3),
         "feq": {"events": int(events), "a2": a2, "r": r, "lambda2": lam, "overflow": ovf,
