@@ -201,6 +201,23 @@ typedef struct {
 } lj_md_info_t;
 mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info);
 
+/* Checkpoint: write the handle's replicas to the file `path` (binary, the
+ * host's byte order): the lj_params given at init, the MD steps done, and per
+ * particle in caller order the wrapped position, the full-step velocity and
+ * the image counts (as lj_md_get_state returns them).  Coarse-graining
+ * attachments and their accumulators are not saved.  Synchronises `stream`;
+ * refuses a handle with a recorded device fault.  EINVAL when the file cannot
+ * be written. */
+mdlg_status lj_md_save(lj_md* md, const char* path, void* stream);
+
+/* Resume: a new handle from a file written by lj_md_save, with the same
+ * replicas, parameters and caller order, the saved positions, velocities and
+ * image counts, and steps_done as saved.  The cell lists are built afresh,
+ * so the continuation equals the uninterrupted run up to the summation order
+ * of the pair forces.  EINVAL for a missing, foreign or truncated file.
+ * Synchronises `stream`. */
+mdlg_status lj_md_load(lj_md** out, const char* path, void* stream);
+
 /* Free the handle and its device memory (NULL-safe). */
 void lj_md_destroy(lj_md* md);
 

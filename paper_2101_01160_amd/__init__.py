@@ -15,6 +15,7 @@ Quick use::
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -25,7 +26,8 @@ from ._abi import Info, LJParams, Lattice, MDLGError
 __all__ = [
     "MDLGError", "LJParams", "Lattice", "LJSystem", "CGAccumulators",
     "lj_params", "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
-    "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_destroy",
+    "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_save", "lj_md_load",
+    "lj_md_destroy",
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
@@ -143,6 +145,16 @@ def lj_md_get_state(h, pos=None, vel=None, img=None, stream=None):
     _abi.check(_abi.lib().lj_md_get_state(h, _dev(pos, torch.float64, None, "pos"),
                                           _dev(vel, torch.float64, None, "vel"),
                                           _dev(img, torch.int32, None, "img"), _stream(stream)))
+
+
+def lj_md_save(h, path, stream=None):
+    _abi.check(_abi.lib().lj_md_save(h, os.fsencode(path), _stream(stream)))
+
+
+def lj_md_load(path, stream=None) -> C.c_void_p:
+    h = C.c_void_p()
+    _abi.check(_abi.lib().lj_md_load(C.byref(h), os.fsencode(path), _stream(stream)))
+    return h
 
 
 def lj_md_forces(h, force, stream=None):
@@ -490,6 +502,22 @@ class LJSystem:
         if self.handle:
             lj_md_destroy(self.handle)
             self.handle = None
+
+    def save(self, path):
+        lj_md_save(self.handle, path, self.stream)
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A system resumed from a file written by save()."""
+        obj = cls.__new__(cls)
+        obj.handle = lj_md_load(path, stream)
+        obj.stream = stream
+        info = lj_md_info(obj.handle)
+        obj.n_rep = info["n_rep"]
+        obj.n_total = info["n_total"]
+        obj.params = None
+        obj.cg = None
+        return obj
 
     def __del__(self):
         try:

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "MDLG_OK", -1: "MDLG_EINVAL", -2: "MDLG_ENOMEM", -3: "MDLG_EH
 EXPORTS = [
     "mdlg_last_error", "mdlg_version", "mdlg_velocity_table",
     "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
-    "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_destroy",
+    "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_save", "lj_md_load", "lj_md_destroy",
     "lj_md_autotune",
     "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg",
@@ -118,6 +118,8 @@ def lib() -> C.CDLL:
         "lj_md_energy": (i32, [vp, vp, vp]),
         "lj_md_check": (i32, [vp, vp]),
         "lj_md_info": (i32, [vp, P(Info)]),
+        "lj_md_save": (i32, [vp, C.c_char_p, vp]),
+        "lj_md_load": (i32, [P(vp), C.c_char_p, vp]),
         "lj_md_destroy": (None, [vp]),
         "lj_md_autotune": (i32, [i32, P(LJParams), vp, vp, i32, P(Lattice), i32, P(LJParams), P(dbl), vp]),
         "mdlg_coarse_grain": (i32, [P(Lattice), dbl, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]),

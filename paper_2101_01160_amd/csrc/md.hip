@@ -25,6 +25,7 @@
 // and writes fixed-order moment partials.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <array>
@@ -1358,6 +1359,12 @@ __global__ void k_fill_f64(double* p, long long n, double v) {
 
 __global__ void k_set_i64(long long* p, long long v) { *p = v; }
 
+// Image counts given in caller order moved to the slots (pad slots keep theirs).
+__global__ void k_put_img(const int2* __restrict__ img_in, const int* __restrict__ id, int S, int2* __restrict__ img) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S && id[s] >= 0) img[s] = img_in[id[s]];
+}
+
 // Exclusive scan of n ints (cnt) into out[0..n] (out[n] = total), three passes
 // over tiles of 4096 elements (1024 threads x 4).
 constexpr int kScanTile = 4096;
@@ -1562,6 +1569,7 @@ hipError_t dalloc(T** p, size_t n) {
 }  // namespace
 
 struct lj_md {
+    std::vector<lj_params> params;  // as given at init (saved by lj_md_save)
     int R = 0;
     int S = 0;   // total slots
     int C = 0;   // total cells including one sentinel per replica
@@ -2018,6 +2026,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     md->ubatch = p[0].gather_batch ? p[0].gather_batch : 8;
     if (const char* e = std::getenv("MDLG_TILE_STAGE_MAX")) md->stage_max = std::max(0, std::atoi(e));
     md->dt = p[0].dt;
+    md->params.assign(p, p + n_rep);
     long long slots = 0, cells = 0, poff = 0, ttiles = 0;
     double skin_half_min = 1e300;
     for (int r = 0; r < n_rep; ++r) {
@@ -2501,6 +2510,124 @@ extern "C" mdlg_status lj_md_energy(lj_md* md, double* out, void* stream) {
 extern "C" mdlg_status lj_md_check(lj_md* md, void* stream) {
     if (!md) return fail(MDLG_EINVAL, "lj_md_check: NULL handle");
     return sync_check(md, (hipStream_t)stream);
+}
+
+namespace {
+
+// File layout of lj_md_save (little-endian, as the host stores it)
+struct SaveHeader {
+    char magic[8];            // "MDLGLJMD"
+    uint32_t version;         // 1
+    uint32_t params_bytes;    // sizeof(lj_params)
+    int32_t n_rep;
+    int32_t reserved;
+    int64_t n_total;
+    int64_t steps_done;
+};
+constexpr char kSaveMagic[8] = {'M', 'D', 'L', 'G', 'L', 'J', 'M', 'D'};
+
+struct FileCloser {
+    FILE* f;
+    ~FileCloser() {
+        if (f) std::fclose(f);
+    }
+};
+
+}  // namespace
+
+extern "C" mdlg_status lj_md_save(lj_md* md, const char* path, void* stream) {
+    if (!md || !path) return fail(MDLG_EINVAL, "lj_md_save: NULL argument");
+    if (md->broken) return fail(MDLG_EINVAL, "lj_md_save: handle is unusable after a device fault");
+    hipStream_t st = (hipStream_t)stream;
+    const long long n = md->n_total;
+    std::vector<double> pos(2 * (size_t)n), vel(2 * (size_t)n);
+    std::vector<int32_t> img(2 * (size_t)n);
+    if (n > 0) {
+        unsigned char* dev = nullptr;
+        const size_t bp = sizeof(double) * 2 * (size_t)n, bi = sizeof(int32_t) * 2 * (size_t)n;
+        MDLG_HIP(hipMallocAsync((void**)&dev, 2 * bp + bi, st));
+        hipError_t e = launch_observe(md, st, (double2*)dev, (double2*)(dev + bp), (int2*)(dev + 2 * bp), nullptr, false);
+        if (e == hipSuccess) e = hipMemcpyAsync(pos.data(), dev, bp, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(vel.data(), dev + bp, bp, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(img.data(), dev + 2 * bp, bi, hipMemcpyDeviceToHost, st);
+        const hipError_t e2 = hipFreeAsync(dev, st);
+        const hipError_t e3 = hipStreamSynchronize(st);
+        MDLG_HIP(e);
+        MDLG_HIP(e2);
+        MDLG_HIP(e3);
+    }
+    mdlg_status s = sync_check(md, st);  // never save a faulted state
+    if (s != MDLG_OK) return s;
+    FileCloser fc{std::fopen(path, "wb")};
+    if (!fc.f) return fail(MDLG_EINVAL, std::string("lj_md_save: cannot open ") + path);
+    SaveHeader h{};
+    std::memcpy(h.magic, kSaveMagic, 8);
+    h.version = 1;
+    h.params_bytes = (uint32_t)sizeof(lj_params);
+    h.n_rep = md->R;
+    h.n_total = n;
+    h.steps_done = md->steps_done;
+    bool ok = std::fwrite(&h, sizeof(h), 1, fc.f) == 1 &&
+              std::fwrite(md->params.data(), sizeof(lj_params), md->params.size(), fc.f) == md->params.size();
+    if (ok && n > 0)
+        ok = std::fwrite(pos.data(), sizeof(double), pos.size(), fc.f) == pos.size() &&
+             std::fwrite(vel.data(), sizeof(double), vel.size(), fc.f) == vel.size() &&
+             std::fwrite(img.data(), sizeof(int32_t), img.size(), fc.f) == img.size();
+    if (ok) ok = std::fflush(fc.f) == 0;
+    if (!ok) return fail(MDLG_EINVAL, std::string("lj_md_save: write failed for ") + path);
+    return MDLG_OK;
+}
+
+extern "C" mdlg_status lj_md_load(lj_md** out, const char* path, void* stream) {
+    if (!out || !path) return fail(MDLG_EINVAL, "lj_md_load: NULL argument");
+    *out = nullptr;
+    FileCloser fc{std::fopen(path, "rb")};
+    if (!fc.f) return fail(MDLG_EINVAL, std::string("lj_md_load: cannot open ") + path);
+    SaveHeader h{};
+    if (std::fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1 ||
+        h.params_bytes != sizeof(lj_params) || h.n_rep < 1 || h.n_rep > (1 << 20) || h.n_total < 1)
+        return fail(MDLG_EINVAL, std::string("lj_md_load: not a state file of this library: ") + path);
+    std::vector<lj_params> params((size_t)h.n_rep);
+    if (std::fread(params.data(), sizeof(lj_params), params.size(), fc.f) != params.size())
+        return fail(MDLG_EINVAL, "lj_md_load: truncated file");
+    long long sum = 0;
+    for (const auto& q : params) sum += q.n;
+    if (sum != h.n_total) return fail(MDLG_EINVAL, "lj_md_load: particle counts disagree");
+    const size_t n = (size_t)h.n_total;
+    std::vector<double> pos(2 * n), vel(2 * n);
+    std::vector<int32_t> img(2 * n);
+    if (std::fread(pos.data(), sizeof(double), pos.size(), fc.f) != pos.size() ||
+        std::fread(vel.data(), sizeof(double), vel.size(), fc.f) != vel.size() ||
+        std::fread(img.data(), sizeof(int32_t), img.size(), fc.f) != img.size())
+        return fail(MDLG_EINVAL, "lj_md_load: truncated file");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bp = sizeof(double) * 2 * n, bi = sizeof(int32_t) * 2 * n;
+    unsigned char* dev = nullptr;
+    MDLG_HIP(hipMalloc((void**)&dev, 2 * bp + bi));
+    hipError_t e = hipMemcpy(dev, pos.data(), bp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dev + bp, vel.data(), bp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dev + 2 * bp, img.data(), bi, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return fail(MDLG_EHIP, std::string("lj_md_load: ") + hipGetErrorString(e));
+    }
+    lj_md* md = nullptr;
+    mdlg_status s = lj_md_init_batch(&md, h.n_rep, params.data(), (const double*)dev, (const double*)(dev + bp), stream);
+    if (s == MDLG_OK) {
+        hipLaunchKernelGGL(k_put_img, dim3((md->S + 255) / 256), dim3(256), 0, st, (const int2*)(dev + 2 * bp),
+                           (const int*)md->id[md->opar], md->S, md->img[md->opar]);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s = fail(MDLG_EHIP, std::string("lj_md_load: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(dev);
+    if (s != MDLG_OK) {
+        lj_md_destroy(md);
+        return s;
+    }
+    md->steps_done = h.steps_done;
+    *out = md;
+    return MDLG_OK;
 }
 
 extern "C" mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info) {

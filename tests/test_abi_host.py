@@ -166,3 +166,17 @@ def test_lambda_vacf_matches_oracle():
     for bad in ((t, -c, 1.0), (t[::-1].copy(), c, 1.0), (t, c, 0.0)):
         with pytest.raises(m.MDLGError):
             m.mdlg_lambda_vacf(*bad)
+
+
+def test_state_load_rejects_missing_and_foreign_files(tmp_path):
+    """The file is read and checked before any device call (stream NULL)."""
+    import ctypes
+
+    from paper_2101_01160_amd import _abi
+    bad = tmp_path / "foreign.state"
+    bad.write_bytes(b"not a state file" * 8)
+    for path in (tmp_path / "missing.state", bad):
+        h = ctypes.c_void_p()
+        assert _abi.lib().lj_md_load(ctypes.byref(h), str(path).encode(), None) == -1  # MDLG_EINVAL
+        assert not h.value
+        assert b"lj_md_load" in _abi.lib().mdlg_last_error()
