@@ -1077,24 +1077,32 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
             const int g = seg_of(q, nr);
             const int s = sa[g] + (q - so[g]);
             const int nn = nbc[s];
-            for (int j = 0; j < nn; ++j) {
-                int kr = (s - slot0) + nbl[(long long)j * S + s];
-                kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
-                const int k = slot0 + kr;
-                // last sorted segment starting at or before k
-                int lo = 0, hi = ne - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (ss[mid] <= k) lo = mid;
-                    else hi = mid - 1;
+            // list rows kListU at a time, issued together (they always exist, see list_rows)
+            for (int j0 = 0; j0 < nn; j0 += kListU) {
+                int rows[kListU];
+                list_rows(nbl, (unsigned int)s + (unsigned int)j0 * (unsigned int)S, (unsigned int)S, rows);
+#pragma unroll
+                for (int u = 0; u < kListU; ++u) {
+                    const int j = j0 + u;
+                    if (j >= nn) break;
+                    int kr = (s - slot0) + rows[u];
+                    kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
+                    const int k = slot0 + kr;
+                    // last sorted segment starting at or before k
+                    int lo = 0, hi = ne - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (ss[mid] <= k) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    int loc = -1;
+                    if (ne > 0 && ss[lo] <= k && k < se[lo]) loc = sl[lo] + (k - ss[lo]);
+                    if (loc < 0 || loc >= tot) {
+                        atomicOr(err, ERR_NLIST);
+                        loc = 0;
+                    }
+                    nbl2[(long long)j * S + s] = (unsigned short)loc;
                 }
-                int loc = -1;
-                if (ne > 0 && ss[lo] <= k && k < se[lo]) loc = sl[lo] + (k - ss[lo]);
-                if (loc < 0 || loc >= tot) {
-                    atomicOr(err, ERR_NLIST);
-                    loc = 0;
-                }
-                nbl2[(long long)j * S + s] = (unsigned short)loc;
             }
         }
     }
