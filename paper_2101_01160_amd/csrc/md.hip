@@ -86,9 +86,11 @@ struct StepArgs {
     const unsigned char* __restrict__ nbc;  // neighbour counts [S]
     // two-step launches
     double2* __restrict__ vout;                 // velocities written by the two-step kernel
-    const int* __restrict__ plist;              // [tiles][kPairCap]: owned slots, then halo slots
-    const int2* __restrict__ pcnt;              // [tiles]: (owned, staged)
-    const unsigned short* __restrict__ nbl2;    // [maxnb][S]: neighbour as index into its tile's list
+    const int* __restrict__ plist;              // [tiles][kPairCap]: owned, ring-1, ring-2 slots
+    const int4* __restrict__ pcnt;              // [tiles]: (owned, owned + ring 1, staged, 0)
+    const unsigned short* __restrict__ tlist;   // [tiles][maxnb][kPairCap]: neighbours as staged indices
+    const unsigned char* __restrict__ tcnt;     // [tiles][kPairCap]: neighbour counts of owned and ring 1
+    int maxnb;
     const int* __restrict__ ptile_rep;          // [tiles] replica
     int* __restrict__ cell_acc;
     const long long* __restrict__ event_k;
@@ -950,31 +952,38 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
 
 // Two consecutive ordinary steps per launch.  The box is cut into square tiles
 // of pT x pT cells; a block owns the particles of one tile.  Its staged set is
-// those particles followed by the particles of the one-cell ring around the
-// tile, which holds every neighbour of an owned particle (neighbour lists
-// reach one cell width).  First step: every staged particle is advanced, its
-// neighbours read from global memory at time t, and the new positions kept in
-// LDS (halo particles are advanced by their own tiles too: the work is
-// repeated, not shared).  Second step: owned particles only, with neighbours
-// read from LDS through lists of staged indices built at the rebuild.  Both
-// steps run the same force and update code as the one-step kernel, in the
-// same neighbour order, so the result equals two one-step launches bit for
-// bit.  Velocities go to a second buffer: other tiles still read the old ones.
-constexpr int kPairCap = 768;   // staged particles of one tile, owned + halo
-constexpr int kStep2BS = 512;   // threads of the two-step kernel
-constexpr int kPairAutoT = 16;  // smallest tile side (cells) of the default two-step choice
-constexpr int kPairSeg = 104;   // row segments of one tile: 3 pT + 6 <= 102
+// those particles (owned), then the particles of the one-cell ring around the
+// tile (ring 1), then those of the next ring (ring 2).  Neighbour lists reach
+// one cell width, so ring 2 holds every neighbour of a ring-1 particle and
+// ring 1 every neighbour of an owned one.  The block loads the staged
+// positions (and the velocities of owned and ring-1 particles) into LDS once;
+// the first step advances owned and ring-1 particles from LDS (ring-1
+// particles are advanced by their own tiles too: the work is repeated, not
+// shared), the second step the owned ones, both through per-tile neighbour
+// lists of staged indices built at the rebuild.  Both steps run the same force
+// and update code as the one-step kernel, in the same neighbour order, so the
+// result equals two one-step launches bit for bit.  Velocities go to a second
+// buffer: other tiles still read the old ones.
+constexpr int kPairCap = 768;     // staged particles of one tile (owned + two rings)
+constexpr int kStep2BS = 512;     // threads of the two-step kernel
+constexpr int kPairAutoT = 16;    // smallest tile side (cells) of the default two-step choice
+constexpr int kPairTarget = 520;  // staged particles aimed at when choosing the tile side
+constexpr int kPairSeg = 176;     // row segments of one tile: 5 pT + 16 <= 176 for pT <= 32
 
-// Per tile, after the neighbour lists: the staged slots (owned rows, then the
-// two halo rows and the two halo columns, each as contiguous slot ranges of
-// the row-major cell order) and the owned particles' neighbour lists as
-// staged indices.  A tile that stages more than kPairCap particles, or a
-// neighbour outside the staged set, raises ERR_NLIST.
+// Per tile, after the neighbour lists: the staged slots, as contiguous slot
+// ranges of the row-major cell order (owned rows; then ring 1: the rows above
+// and below and the cells left and right of each owned row; then ring 2
+// likewise one cell further out), the counts (owned, owned + ring 1, staged),
+// and for owned and ring-1 particles their neighbour counts and lists as
+// staged indices, [tile][row j][staged index q].  A tile that stages more than
+// kPairCap particles, or a neighbour outside the staged set (or outside
+// owned + ring 1 for an owned particle), raises ERR_NLIST.
 __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
                                                     const int* __restrict__ ptrep, const short* __restrict__ nbl,
-                                                    const unsigned char* __restrict__ nbc, int S, int* __restrict__ plist,
-                                                    int2* __restrict__ pcnt, unsigned short* __restrict__ nbl2,
-                                                    int* err) {
+                                                    const unsigned char* __restrict__ nbc, int S, int maxnb,
+                                                    int* __restrict__ plist, int4* __restrict__ pcnt,
+                                                    unsigned short* __restrict__ tlist,
+                                                    unsigned char* __restrict__ tcnt, int* err) {
     __shared__ int sa[kPairSeg], sn[kPairSeg], so[kPairSeg + 1];
     const int t = blockIdx.x;
     const RepDev& R = reps[ptrep[t]];
@@ -982,63 +991,80 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
     const int lt = t - R.pt0, ty = lt / R.pts, tx = lt % R.pts;
     const int c0 = tx * T, c1 = min(c0 + T, nc), r0 = ty * T, r1 = min(r0 + T, nc);
     const int nr = r1 - r0;
-    const int cl = c0 - 1 < 0 ? nc - 1 : c0 - 1;  // left halo column
-    const int cr = c1 >= nc ? 0 : c1;             // right halo column
-    const bool inner = c0 >= 1 && c1 <= nc - 1;    // halo rows as one range c0 - 1 .. c1
-    const int hs = inner ? 1 : 3;
-    const int ns = nr + 2 * hs + 2 * nr;
-    // segment q: owned rows, then the two halo rows, then the halo cells left
-    // and right of every owned row; each a range of cells ca .. cb - 1 of a row
+    // Segments: owned rows [0, nr); ring 1: the rows above and below as two
+    // pieces each (the part inside the box, the part wrapped across it), then
+    // the cells left and right of each owned row [nr, 3 nr + 4); ring 2 likewise
+    // one cell further out [3 nr + 4, 5 nr + 12).  nc >= pT + 4 keeps every
+    // cell distinct.
+    const int ns = 5 * nr + 12;
     for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-        int row, ca, cb;
+        int row, a, b, piece = -1;  // columns [a, b) before wrapping; piece >= 0: a row range
         if (q < nr) {
             row = r0 + q;
-            ca = c0;
-            cb = c1;
-        } else if (q < nr + 2 * hs) {
-            const int h = (q - nr) / hs, k = (q - nr) % hs;
-            row = h == 0 ? r0 - 1 : r1;
-            row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
-            if (inner) {
-                ca = c0 - 1;
-                cb = c1 + 1;
-            } else {
-                ca = k == 0 ? c0 : (k == 1 ? cl : cr);
-                cb = k == 0 ? c1 : ca + 1;
-            }
+            a = c0;
+            b = c1;
+        } else if (q < nr + 4) {
+            const int k = q - nr;
+            row = (k >> 1) ? r1 : r0 - 1;
+            a = c0 - 1;
+            b = c1 + 1;
+            piece = k & 1;
+        } else if (q < 3 * nr + 4) {
+            const int k = q - nr - 4;
+            row = r0 + (k >> 1);
+            a = (k & 1) ? c1 : c0 - 1;
+            b = a + 1;
+        } else if (q < 3 * nr + 8) {
+            const int k = q - 3 * nr - 4;
+            row = (k >> 1) ? r1 + 1 : r0 - 2;
+            a = c0 - 2;
+            b = c1 + 2;
+            piece = k & 1;
         } else {
-            const int k = q - nr - 2 * hs;
-            row = r0 + k / 2;
-            ca = (k & 1) ? cr : cl;
-            cb = ca + 1;
+            const int k = q - 3 * nr - 8;
+            row = r0 - 1 + (k >> 1);
+            a = (k & 1) ? c1 + 1 : c0 - 2;
+            b = a + 1;
+        }
+        row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
+        int ca, cb;
+        if (piece < 0) {
+            ca = a < 0 ? a + nc : (a >= nc ? a - nc : a);  // one cell, or an owned row inside the box
+            cb = ca + (b - a);
+        } else if (piece == 0) {
+            ca = max(a, 0);
+            cb = min(b, nc);
+        } else if (a < 0) {
+            ca = a + nc;
+            cb = nc;
+        } else if (b > nc) {
+            ca = 0;
+            cb = b - nc;
+        } else {
+            ca = 0;
+            cb = 0;
         }
         const int base = R.cell0 + row * nc;
         sa[q] = cs[base + ca];
         sn[q] = cs[base + cb] - sa[q];
     }
-    for (int q = ns + threadIdx.x; q < kPairSeg; q += blockDim.x) sn[q] = 0;
-    __syncthreads();
-    // exclusive prefix of the segment lengths (Hillis-Steele over 128 entries)
-    __shared__ int scan[2][128];
-    for (int q = threadIdx.x; q < 128; q += blockDim.x) scan[0][q] = q < ns ? sn[q] : 0;
-    __syncthreads();
-    int cur = 0;
-    for (int d = 1; d < 128; d *= 2) {
-        for (int q = threadIdx.x; q < 128; q += blockDim.x)
-            scan[cur ^ 1][q] = scan[cur][q] + (q >= d ? scan[cur][q - d] : 0);
-        __syncthreads();
-        cur ^= 1;
-    }
-    for (int q = threadIdx.x; q <= ns; q += blockDim.x) so[q] = q == 0 ? 0 : scan[cur][q - 1];
     __syncthreads();
     if (threadIdx.x == 0) {
-        int tot = so[ns];
-        if (tot > kPairCap) {
-            atomicOr(err, ERR_NLIST);
-            tot = kPairCap;
+        int acc = 0;
+        for (int q = 0; q < ns; ++q) {
+            so[q] = acc;
+            acc += sn[q];
         }
-        pcnt[t] = make_int2(min(so[nr], kPairCap), tot);
+        so[ns] = acc;
     }
+    __syncthreads();
+    const int own = min(so[nr], kPairCap), mid = min(so[3 * nr + 4], kPairCap);
+    int tot = so[ns];
+    if (tot > kPairCap) {
+        if (threadIdx.x == 0) atomicOr(err, ERR_NLIST);
+        tot = kPairCap;
+    }
+    if (threadIdx.x == 0) pcnt[t] = make_int4(own, mid, tot, 0);
     // non-empty segments sorted by first slot, for the staged index of a slot
     __shared__ int ss[kPairSeg], se[kPairSeg], sl[kPairSeg];
     __shared__ int nne;
@@ -1047,62 +1073,63 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
     for (int g = threadIdx.x; g < ns; g += blockDim.x) {
         if (sn[g] == 0) continue;
         int rank = 0;
-        for (int h = 0; h < ns; ++h) rank += (sn[h] > 0 && sa[h] < sa[g]) ? 1 : 0;
+        for (int h = 0; h < ns; ++h) rank += (sn[h] > 0 && (sa[h] < sa[g] || (sa[h] == sa[g] && h < g))) ? 1 : 0;
         ss[rank] = sa[g];
         se[rank] = sa[g] + sn[g];
         sl[rank] = so[g];
         atomicAdd(&nne, 1);
     }
     __syncthreads();
-    const int tot = min(so[ns], kPairCap), own = min(so[nr], kPairCap), ne = nne;
+    const int ne = nne;
     int* list = plist + (long long)t * kPairCap;
-    // segment of staged index q: the last g < nseg with so[g] <= q
-    auto seg_of = [&](int q, int nseg) {
-        int lo = 0, hi = nseg - 1;
+    // segment of staged index q: the last g with so[g] <= q (among segments 0 .. ns - 1)
+    auto seg_of = [&](int q) {
+        int lo = 0, hi = ns - 1;
         while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (so[mid] <= q) lo = mid;
-            else hi = mid - 1;
+            const int m = (lo + hi + 1) >> 1;
+            if (so[m] <= q) lo = m;
+            else hi = m - 1;
         }
         return lo;
     };
     for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-        const int g = seg_of(q, ns);
+        const int g = seg_of(q);
         list[q] = sa[g] + (q - so[g]);
     }
-    // owned particles' neighbour lists as staged indices
+    // owned and ring-1 particles: neighbour counts and lists as staged indices
     const int slot0 = R.slot0, nrep = R.n;
-    for (int q = threadIdx.x; q < own; q += blockDim.x) {
-        {
-            const int g = seg_of(q, nr);
-            const int s = sa[g] + (q - so[g]);
-            const int nn = nbc[s];
-            // list rows kListU at a time, issued together (they always exist, see list_rows)
-            for (int j0 = 0; j0 < nn; j0 += kListU) {
-                int rows[kListU];
-                list_rows(nbl, (unsigned int)s + (unsigned int)j0 * (unsigned int)S, (unsigned int)S, rows);
+    unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
+    for (int q = threadIdx.x; q < mid; q += blockDim.x) {
+        const int g = seg_of(q);
+        const int s = sa[g] + (q - so[g]);
+        const int nn = nbc[s];
+        tcnt[(long long)t * kPairCap + q] = (unsigned char)nn;
+        const int lim = q < own ? mid : tot;
+        // list rows kListU at a time, issued together (they always exist, see list_rows)
+        for (int j0 = 0; j0 < nn; j0 += kListU) {
+            int rows[kListU];
+            list_rows(nbl, (unsigned int)s + (unsigned int)j0 * (unsigned int)S, (unsigned int)S, rows);
 #pragma unroll
-                for (int u = 0; u < kListU; ++u) {
-                    const int j = j0 + u;
-                    if (j >= nn) break;
-                    int kr = (s - slot0) + rows[u];
-                    kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
-                    const int k = slot0 + kr;
-                    // last sorted segment starting at or before k
-                    int lo = 0, hi = ne - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (ss[mid] <= k) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    int loc = -1;
-                    if (ne > 0 && ss[lo] <= k && k < se[lo]) loc = sl[lo] + (k - ss[lo]);
-                    if (loc < 0 || loc >= tot) {
-                        atomicOr(err, ERR_NLIST);
-                        loc = 0;
-                    }
-                    nbl2[(long long)j * S + s] = (unsigned short)loc;
+            for (int u = 0; u < kListU; ++u) {
+                const int j = j0 + u;
+                if (j >= nn) break;
+                int kr = (s - slot0) + rows[u];
+                kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
+                const int k = slot0 + kr;
+                // last sorted segment starting at or before k
+                int lo = 0, hi = ne - 1;
+                while (lo < hi) {
+                    const int m = (lo + hi + 1) >> 1;
+                    if (ss[m] <= k) lo = m;
+                    else hi = m - 1;
                 }
+                int loc = -1;
+                if (ne > 0 && ss[lo] <= k && k < se[lo]) loc = sl[lo] + (k - ss[lo]);
+                if (loc < 0 || loc >= lim) {
+                    atomicOr(err, ERR_NLIST);
+                    loc = 0;
+                }
+                tl[(long long)j * kPairCap + q] = (unsigned short)loc;
             }
         }
     }
@@ -1110,68 +1137,73 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
 
 template <int BS, bool F32>
 __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
-    __shared__ double2 xs[kPairCap];
-    __shared__ double2 vs[kPairCap];
-    __shared__ char2 wr[kPairCap];
+    __shared__ double2 x0[kPairCap];  // staged positions at time t
+    __shared__ double2 x1[kPairCap];  // owned and ring-1 positions after the first step
+    __shared__ double2 vs[kPairCap];  // owned and ring-1 velocities
+    __shared__ char2 wr[kPairCap];    // first-step image changes of owned particles
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
     const RepDev& R = a.reps[r];
     const double L = R.L;
     const double invL = 1.0 / L;
-    const int2 c = a.pcnt[t];
-    const int own = c.x, tot = c.y;
+    const int4 c = a.pcnt[t];
+    const int own = c.x, mid = c.y, tot = c.z;
     const int* __restrict__ list = a.plist + (long long)t * kPairCap;
-    // A tile two cells or more from every box edge stages particles, and has
-    // neighbours of them, only within the box: separations need no image.
+    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
+    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    // A tile three cells or more from every box edge stages particles of cells
+    // 1 .. nc - 2 only; they move less than a cell between rebuilds, so none
+    // crosses the periodic boundary and separations need no image.
     const int nc = R.nc, T = R.pT, lt = t - R.pt0;
     const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
     const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
-    const bool interior = c0 >= 2 && r0 >= 2 && c1 <= nc - 2 && r1 <= nc - 2;
+    const bool interior = c0 >= 3 && r0 >= 3 && c1 <= nc - 3 && r1 <= nc - 3;
     const double2* __restrict__ pin = a.pin;
-    const int nr = R.n, slot0 = R.slot0;
-    const unsigned int S = (unsigned int)a.nslots;
-    // the thread's first owned particle: its slot, count and first list rows for
-    // the second step, loaded before the barrier
+    const unsigned int SL = (unsigned int)kPairCap;
+    // the thread's first staged particle: its slot, and when it is owned or in
+    // ring 1 its neighbour count and first list rows, loaded with the positions
+    const int qf = threadIdx.x;
     int s_first = 0, nn_first = 0;
     int pre[kListU] = {0, 0, 0, 0};
+    if (qf < mid) {
+        nn_first = tc[qf];
+        list_rows(tl, (unsigned int)qf, SL, pre);
+    }
     for (int q = threadIdx.x; q < tot; q += BS) {
         const int s = list[q];
-        const double2 p = pin[s];
-        double2 v = a.vel[s];
-        const int nn = a.nbc[s];
-        if (q == (int)threadIdx.x && q < own) {
-            s_first = s;
-            nn_first = nn;
-            list_rows(a.nbl2, (unsigned int)s, S, pre);
-        }
-        const int srel = s - slot0;
-        auto fetch = [&](int k) {
-            int kr = srel + k;
-            kr = kr < 0 ? kr + nr : (kr >= nr ? kr - nr : kr);
-            return pin[slot0 + kr];
-        };
-        double fx, fy;
-        nlist_force<F32>(p, nn, a.nbl, (unsigned int)s, S, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
-                         R.eps24f, fx, fy);
-        int wx, wy;
-        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        xs[q] = pn;
-        if (q < own) {
-            vs[q] = v;
-            wr[q] = make_char2((signed char)wx, (signed char)wy);
-        }
+        if (q == qf) s_first = s;
+        x0[q] = pin[s];
+        if (q < mid) vs[q] = a.vel[s];
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < own; q += BS) {
-        const bool firstq = q == (int)threadIdx.x;
-        const int s = firstq ? s_first : list[q];
-        const double2 p = xs[q];
+    // first step: owned and ring-1 particles
+    for (int q = threadIdx.x; q < mid; q += BS) {
+        const bool firstq = q == qf;
+        const double2 p = x0[q];
         double2 v = vs[q];
-        const int nn = firstq ? nn_first : a.nbc[s];
-        auto fetch = [&](int k) { return xs[k]; };
+        const int nn = firstq ? nn_first : tc[q];
+        auto fetch = [&](int k) { return x0[k]; };
         double fx, fy;
-        nlist_force<F32>(p, nn, a.nbl2, (unsigned int)s, S, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
-                         R.eps24f, fx, fy, pre, firstq);
+        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+                         fx, fy, pre, firstq);
+        int wx, wy;
+        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        x1[q] = pn;
+        vs[q] = v;
+        if (q < own) wr[q] = make_char2((signed char)wx, (signed char)wy);
+    }
+    __syncthreads();
+    // second step: owned particles, the same lists into the first step's positions
+    for (int q = threadIdx.x; q < own; q += BS) {
+        const bool firstq = q == qf;
+        const int s = firstq ? s_first : list[q];
+        const double2 p = x1[q];
+        double2 v = vs[q];
+        const int nn = firstq ? nn_first : tc[q];
+        auto fetch = [&](int k) { return x1[k]; };
+        double fx, fy;
+        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+                         fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
         const char2 w1 = wr[q];
@@ -1602,8 +1634,9 @@ struct lj_md {
     int npt = 0;                      // two-step tiles
     int* d_ptrep = nullptr;           // [npt] replica
     int* plist = nullptr;             // [npt][kPairCap]
-    int2* pcnt = nullptr;             // [npt]
-    unsigned short* nbl2 = nullptr;   // [maxnb][S]
+    int4* pcnt = nullptr;             // [npt]
+    unsigned short* tlist = nullptr;  // [npt][maxnb][kPairCap]
+    unsigned char* tcnt = nullptr;    // [npt][kPairCap]
     double2* pref = nullptr;  // positions at the list build
     int maxnb = 0;
     int* d_hpart = nullptr;
@@ -1706,7 +1739,9 @@ StepArgs make_args(lj_md* md) {
     a.nbc = md->nbc;
     a.plist = md->plist;
     a.pcnt = md->pcnt;
-    a.nbl2 = md->nbl2;
+    a.tlist = md->tlist;
+    a.tcnt = md->tcnt;
+    a.maxnb = md->maxnb;
     a.ptile_rep = md->d_ptrep;
     a.cell_acc = md->cell_acc;
     a.event_k = md->d_event_k;
@@ -1862,7 +1897,8 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     if (md->two_step)
         hipLaunchKernelGGL(k_pair_build, dim3(md->npt), dim3(256), 0, st, (const int*)md->cs,
                            (const RepDev*)md->d_reps, (const int*)md->d_ptrep, (const short*)md->nbl,
-                           (const unsigned char*)md->nbc, S, md->plist, md->pcnt, md->nbl2, md->d_err);
+                           (const unsigned char*)md->nbc, S, md->maxnb, md->plist, md->pcnt, md->tlist, md->tcnt,
+                           md->d_err);
     md->ppar ^= 1;
     md->opar ^= 1;
     md->vpar ^= 1;
@@ -2095,9 +2131,9 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     }
     md->TT = (int)ttiles;
     md->nscan = (md->C + kScanTile - 1) / kScanTile;
-    // two-step tiles: about 460 staged particles on average, so that one
-    // block of kStep2BS threads advances a tile in one pass per step; a ring
-    // of distinct cells needs nc >= pT + 2
+    // two-step tiles: about kPairTarget staged particles on average (owned and
+    // two rings), so that one block of kStep2BS threads advances a tile in
+    // about one pass per step; two rings of distinct cells need nc >= pT + 4
     // (fuse_steps 0: only where tiles are at least kPairAutoT cells wide, so
     // that the halo adds at most ~30% to the first step; 2: wherever the
     // geometry allows)
@@ -2108,8 +2144,8 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
         for (int r = 0; r < n_rep && md->two_step; ++r) {
             RepDev& d = md->reps[r].d;
             const double ppc = std::max((double)d.n / ((double)d.nc * d.nc), 1e-9);
-            int T = (int)std::floor(std::sqrt(460.0 / ppc)) - 2;
-            T = std::min(std::min(T, 32), d.nc - 2);
+            int T = (int)std::floor(std::sqrt((double)kPairTarget / ppc)) - 4;
+            T = std::min(std::min(T, 32), d.nc - 4);
             if (T < tmin) {
                 md->two_step = false;
                 break;
@@ -2161,7 +2197,8 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
         ok = A(dalloc(&md->nbl, (size_t)md->maxnb * md->S)) && A(dalloc(&md->nbc, md->S)) && A(dalloc(&md->pref, md->S));
         if (ok && md->two_step)
             ok = A(dalloc(&md->d_ptrep, md->npt)) && A(dalloc(&md->plist, (size_t)md->npt * kPairCap)) &&
-                 A(dalloc(&md->pcnt, md->npt)) && A(dalloc(&md->nbl2, (size_t)md->maxnb * md->S));
+                 A(dalloc(&md->pcnt, md->npt)) && A(dalloc(&md->tlist, (size_t)md->npt * md->maxnb * kPairCap)) &&
+                 A(dalloc(&md->tcnt, (size_t)md->npt * kPairCap));
     }
     if (!ok) return destroy_on_fail(md, fail(MDLG_ENOMEM, "lj_md_init: device allocation failed"));
 
@@ -2660,7 +2697,7 @@ extern "C" void lj_md_destroy(lj_md* md) {
     void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->d_done, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
                     md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm, md->permid,
                     md->cellof, md->cnt, md->cs, md->bsum, md->d_err, md->d_epart, md->d_eout, md->d_vmax,
-                    md->d_mpart, md->d_event_k, md->d_ptrep, md->plist, md->pcnt, md->nbl2};
+                    md->d_mpart, md->d_event_k, md->d_ptrep, md->plist, md->pcnt, md->tlist, md->tcnt};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete md;
