@@ -264,7 +264,7 @@ def main():
                    "block_size": info["block_size"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("MD step kernel, two ordinary steps per launch" if spl == 2 else
+                     "kernel": (f"MD step kernel, {spl} ordinary steps per launch" if spl > 1 else
                                 "MD step kernel (no coarse-graining event)"),
                      "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl},
         "us_per_md_step": ms * 1e3 / md_steps,
@@ -684,7 +684,7 @@ def bench_paper(args):
                    "replicas": R, "events_per_row": E, "equil_steps": args.equil},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "MD step kernel" + (", two ordinary steps per launch" if spl == 2 else ""),
+                     "kernel": "MD step kernel" + (f", {spl} ordinary steps per launch" if spl > 1 else ""),
                      "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl},
         "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
                       "launches": [int(x) for x in kcnt], "displacement_hist_total": hist_ms, "vacf": vacf_ms},

@@ -94,13 +94,16 @@ typedef struct {
                                cells                                              */
     int32_t gather_batch;   /* kernel 1: neighbour loads issued per batch, 0 = 8;
                                4, 8 or 16                                         */
-    int32_t fuse_steps;     /* kernel 3: two consecutive ordinary steps per
-                               launch (square tiles of cells with a one-cell
-                               halo; the first step's positions stay in LDS):
-                               0 = where the tiles are at least 16 cells wide
-                               (dilute systems, where the halo is cheap),
-                               1 = never, 2 = wherever the geometry allows.
-                               Results are the same bit for bit.               */
+    int32_t fuse_steps;     /* kernel 3: consecutive ordinary steps per launch
+                               (square tiles of cells staged in LDS with one
+                               ring of halo cells per step; the intermediate
+                               positions stay in LDS): 0 = three where such
+                               tiles are at least 16 cells wide, else two where
+                               the two-step tiles are (dilute systems, where
+                               the halo is cheap), else one; 1 = one; 2 = two
+                               wherever the geometry allows; 3 = three wherever
+                               it allows, else two.  Results are the same bit
+                               for bit.                                        */
 } lj_params;
 
 typedef struct lj_md lj_md; /* opaque handle; owns all device state */
@@ -196,7 +199,7 @@ typedef struct {
     int32_t cells_per_side; /* cell-list cells per side of replica 0            */
     int32_t block_size;
     double cell_width;      /* of replica 0                                     */
-    int32_t steps_per_launch; /* ordinary MD steps per step-kernel launch: 1 or 2 */
+    int32_t steps_per_launch; /* ordinary MD steps per step-kernel launch: 1, 2 or 3 */
     int32_t reserved;
 } lj_md_info_t;
 mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info);

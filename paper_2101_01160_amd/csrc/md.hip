@@ -964,23 +964,26 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
 // and update code as the one-step kernel, in the same neighbour order, so the
 // result equals two one-step launches bit for bit.  Velocities go to a second
 // buffer: other tiles still read the old ones.
-constexpr int kPairCap = 768;     // staged particles of one tile (owned + two rings)
-constexpr int kStep2BS = 512;     // threads of the two-step kernel
-constexpr int kPairAutoT = 16;    // smallest tile side (cells) of the default two-step choice
-constexpr int kPairTarget = 520;  // staged particles aimed at when choosing the tile side
-constexpr int kPairSeg = 176;     // row segments of one tile: 5 pT + 16 <= 176 for pT <= 32
+constexpr int kPairCap = 768;      // staged particles of one tile (owned + its rings)
+constexpr int kStep2BS = 512;      // threads of the two- and three-step kernels
+constexpr int kPairAutoT = 16;     // smallest tile side (cells) of the default fused choice
+constexpr int kPairTarget = 520;   // staged particles aimed at when choosing the tile side, two rings
+constexpr int kPairTarget3 = 640;  // the same with three rings
+constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248 for pT <= 32, three rings
 
 // Per tile, after the neighbour lists: the staged slots, as contiguous slot
 // ranges of the row-major cell order (owned rows; then ring 1: the rows above
-// and below and the cells left and right of each owned row; then ring 2
-// likewise one cell further out), the counts (owned, owned + ring 1, staged),
-// and for owned and ring-1 particles their neighbour counts and lists as
-// staged indices, [tile][row j][staged index q].  A tile that stages more than
-// kPairCap particles, or a neighbour outside the staged set (or outside
-// owned + ring 1 for an owned particle), raises ERR_NLIST.
+// and below and the cells left and right of each owned row; then ring 2 and,
+// with three rings, ring 3 likewise one cell further out each), the counts
+// (owned, up to ring 1, up to ring 2, all), and for the particles of every ring
+// but the last their neighbour counts and lists as staged indices,
+// [tile][row j][staged index q].  Neighbour lists reach one cell, so the
+// neighbours of a ring-k particle lie within ring k + 1.  A tile that stages
+// more than kPairCap particles, or a neighbour outside that bound, raises
+// ERR_NLIST.
 __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
                                                     const int* __restrict__ ptrep, const short* __restrict__ nbl,
-                                                    const unsigned char* __restrict__ nbc, int S, int maxnb,
+                                                    const unsigned char* __restrict__ nbc, int S, int maxnb, int rings,
                                                     int* __restrict__ plist, int4* __restrict__ pcnt,
                                                     unsigned short* __restrict__ tlist,
                                                     unsigned char* __restrict__ tcnt, int* err) {
@@ -991,40 +994,34 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
     const int lt = t - R.pt0, ty = lt / R.pts, tx = lt % R.pts;
     const int c0 = tx * T, c1 = min(c0 + T, nc), r0 = ty * T, r1 = min(r0 + T, nc);
     const int nr = r1 - r0;
-    // Segments: owned rows [0, nr); ring 1: the rows above and below as two
-    // pieces each (the part inside the box, the part wrapped across it), then
-    // the cells left and right of each owned row [nr, 3 nr + 4); ring 2 likewise
-    // one cell further out [3 nr + 4, 5 nr + 12).  nc >= pT + 4 keeps every
-    // cell distinct.
-    const int ns = 5 * nr + 12;
+    // Segments: owned rows [0, nr); ring k (1 <= k <= rings) from
+    // first(k) = nr + (k - 1) 2 nr + 2 k (k - 1): the rows r0 - k and r1 + k - 1 over
+    // columns [c0 - k, c1 + k) as two pieces each (inside the box, wrapped
+    // across it), then the cells c0 - k and c1 + k - 1 of the rows
+    // r0 - k + 1 .. r1 + k - 2.  nc >= pT + 2 rings keeps every cell distinct.
+    auto first = [&](int k) { return nr + (k - 1) * 2 * nr + 2 * k * (k - 1); };
+    const int ns = first(rings + 1);
     for (int q = threadIdx.x; q < ns; q += blockDim.x) {
         int row, a, b, piece = -1;  // columns [a, b) before wrapping; piece >= 0: a row range
         if (q < nr) {
             row = r0 + q;
             a = c0;
             b = c1;
-        } else if (q < nr + 4) {
-            const int k = q - nr;
-            row = (k >> 1) ? r1 : r0 - 1;
-            a = c0 - 1;
-            b = c1 + 1;
-            piece = k & 1;
-        } else if (q < 3 * nr + 4) {
-            const int k = q - nr - 4;
-            row = r0 + (k >> 1);
-            a = (k & 1) ? c1 : c0 - 1;
-            b = a + 1;
-        } else if (q < 3 * nr + 8) {
-            const int k = q - 3 * nr - 4;
-            row = (k >> 1) ? r1 + 1 : r0 - 2;
-            a = c0 - 2;
-            b = c1 + 2;
-            piece = k & 1;
         } else {
-            const int k = q - 3 * nr - 8;
-            row = r0 - 1 + (k >> 1);
-            a = (k & 1) ? c1 + 1 : c0 - 2;
-            b = a + 1;
+            int k = 1;
+            while (q >= first(k + 1)) ++k;
+            const int e = q - first(k);
+            if (e < 4) {
+                row = (e >> 1) ? r1 + k - 1 : r0 - k;
+                a = c0 - k;
+                b = c1 + k;
+                piece = e & 1;
+            } else {
+                const int f = e - 4;
+                row = r0 - k + 1 + (f >> 1);
+                a = (f & 1) ? c1 + k - 1 : c0 - k;
+                b = a + 1;
+            }
         }
         row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
         int ca, cb;
@@ -1058,13 +1055,16 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
         so[ns] = acc;
     }
     __syncthreads();
-    const int own = min(so[nr], kPairCap), mid = min(so[3 * nr + 4], kPairCap);
+    // staged counts up to each ring: n[0] owned, n[k] owned and rings 1 .. k
+    int n[4];
+    for (int k = 0; k < 4; ++k) n[k] = min(so[first(min(k, rings) + 1)], kPairCap);
+    const int own = n[0];
     int tot = so[ns];
     if (tot > kPairCap) {
         if (threadIdx.x == 0) atomicOr(err, ERR_NLIST);
         tot = kPairCap;
     }
-    if (threadIdx.x == 0) pcnt[t] = make_int4(own, mid, tot, 0);
+    if (threadIdx.x == 0) pcnt[t] = make_int4(own, n[1], n[2], tot);
     // non-empty segments sorted by first slot, for the staged index of a slot
     __shared__ int ss[kPairSeg], se[kPairSeg], sl[kPairSeg];
     __shared__ int nne;
@@ -1096,15 +1096,18 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
         const int g = seg_of(q);
         list[q] = sa[g] + (q - so[g]);
     }
-    // owned and ring-1 particles: neighbour counts and lists as staged indices
+    // particles of every ring but the last: neighbour counts and lists as staged indices
     const int slot0 = R.slot0, nrep = R.n;
     unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
-    for (int q = threadIdx.x; q < mid; q += blockDim.x) {
+    const int listed = n[rings - 1];
+    for (int q = threadIdx.x; q < listed; q += blockDim.x) {
         const int g = seg_of(q);
         const int s = sa[g] + (q - so[g]);
         const int nn = nbc[s];
         tcnt[(long long)t * kPairCap + q] = (unsigned char)nn;
-        const int lim = q < own ? mid : tot;
+        int ring = 0;
+        while (q >= n[ring]) ++ring;
+        const int lim = ring + 1 < rings ? n[ring + 1] : tot;
         // list rows kListU at a time, issued together (they always exist, see list_rows)
         for (int j0 = 0; j0 < nn; j0 += kListU) {
             int rows[kListU];
@@ -1147,7 +1150,7 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     const double L = R.L;
     const double invL = 1.0 / L;
     const int4 c = a.pcnt[t];
-    const int own = c.x, mid = c.y, tot = c.z;
+    const int own = c.x, mid = c.y, tot = c.z;  // two steps stage the owned particles and rings 1, 2
     const int* __restrict__ list = a.plist + (long long)t * kPairCap;
     const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
     const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
@@ -1201,6 +1204,114 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
         double2 v = vs[q];
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return x1[k]; };
+        double fx, fy;
+        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+                         fx, fy, pre, firstq);
+        int wx, wy;
+        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        const char2 w1 = wr[q];
+        wx += w1.x;
+        wy += w1.y;
+        if (wx | wy) {
+            int2 im = a.img[s];
+            im.x += wx;
+            im.y += wy;
+            a.img[s] = im;
+        }
+        if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
+        a.pout[s] = pn;
+        a.vout[s] = v;
+    }
+}
+
+// Three consecutive ordinary steps per launch, the two-step scheme with one
+// more ring: the block stages the owned particles and three rings; step 1
+// advances owned and rings 1, 2, step 2 owned and ring 1, step 3 the owned
+// particles, each from the previous step's positions in LDS through the same
+// per-tile lists.  Equal to three one-step launches bit for bit.
+template <int BS, bool F32>
+__global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
+    __shared__ double2 xa[kPairCap];  // staged positions at time t, then owned and ring 1 after step 2
+    __shared__ double2 xb[kPairCap];  // owned, rings 1 and 2 after step 1
+    __shared__ double2 vs[kPairCap];  // velocities of owned, rings 1 and 2
+    __shared__ char2 wr[kPairCap];    // image changes of owned particles in steps 1 and 2
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
+    const RepDev& R = a.reps[r];
+    const double L = R.L;
+    const double invL = 1.0 / L;
+    const int4 c = a.pcnt[t];
+    const int own = c.x, n1 = c.y, n2 = c.z, tot = c.w;
+    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
+    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
+    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    // staged cells 1 .. nc - 2 only (tiles four cells or more from every edge):
+    // no staged particle crosses the periodic boundary between rebuilds
+    const int nc = R.nc, T = R.pT, lt = t - R.pt0;
+    const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
+    const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
+    const bool interior = c0 >= 4 && r0 >= 4 && c1 <= nc - 4 && r1 <= nc - 4;
+    const double2* __restrict__ pin = a.pin;
+    const unsigned int SL = (unsigned int)kPairCap;
+    const int qf = threadIdx.x;
+    int s_first = 0, nn_first = 0;
+    int pre[kListU] = {0, 0, 0, 0};
+    if (qf < n2) {
+        nn_first = tc[qf];
+        list_rows(tl, (unsigned int)qf, SL, pre);
+    }
+    for (int q = threadIdx.x; q < tot; q += BS) {
+        const int s = list[q];
+        if (q == qf) s_first = s;
+        xa[q] = pin[s];
+        if (q < n2) vs[q] = a.vel[s];
+    }
+    __syncthreads();
+    // step 1: owned, rings 1 and 2, from xa into xb
+    for (int q = threadIdx.x; q < n2; q += BS) {
+        const bool firstq = q == qf;
+        const double2 p = xa[q];
+        double2 v = vs[q];
+        const int nn = firstq ? nn_first : tc[q];
+        auto fetch = [&](int k) { return xa[k]; };
+        double fx, fy;
+        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+                         fx, fy, pre, firstq);
+        int wx, wy;
+        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        xb[q] = pn;
+        vs[q] = v;
+        if (q < own) wr[q] = make_char2((signed char)wx, (signed char)wy);
+    }
+    __syncthreads();
+    // step 2: owned and ring 1, from xb into xa (every read of xa is done)
+    for (int q = threadIdx.x; q < n1; q += BS) {
+        const bool firstq = q == qf;
+        const double2 p = xb[q];
+        double2 v = vs[q];
+        const int nn = firstq ? nn_first : tc[q];
+        auto fetch = [&](int k) { return xb[k]; };
+        double fx, fy;
+        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+                         fx, fy, pre, firstq);
+        int wx, wy;
+        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        xa[q] = pn;
+        vs[q] = v;
+        if (q < own) {
+            const char2 w = wr[q];
+            wr[q] = make_char2((signed char)(w.x + wx), (signed char)(w.y + wy));
+        }
+    }
+    __syncthreads();
+    // step 3: owned particles, from xa to global memory
+    for (int q = threadIdx.x; q < own; q += BS) {
+        const bool firstq = q == qf;
+        const int s = firstq ? s_first : list[q];
+        const double2 p = xa[q];
+        double2 v = vs[q];
+        const int nn = firstq ? nn_first : tc[q];
+        auto fetch = [&](int k) { return xa[k]; };
         double fx, fy;
         nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
@@ -1631,6 +1742,8 @@ struct lj_md {
     unsigned char* nbc = nullptr;
     // two ordinary steps per launch (step kernel 3)
     bool two_step = false;
+    bool three_step = false;          // also three ordinary steps per launch (implies two_step)
+    int rings = 2;                    // cell rings staged per fused tile
     int npt = 0;                      // two-step tiles
     int* d_ptrep = nullptr;           // [npt] replica
     int* plist = nullptr;             // [npt][kPairCap]
@@ -1818,18 +1931,32 @@ hipError_t launch_step2(lj_md* md, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Three ordinary steps in one launch (see k_step3_nlist).
+hipError_t launch_step3(lj_md* md, hipStream_t st) {
+    StepArgs a = make_args(md);
+    const int grid = md->npt;
+    if (md->f32)
+        hipLaunchKernelGGL((k_step3_nlist<kStep2BS, true>), dim3(grid), dim3(kStep2BS), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_step3_nlist<kStep2BS, false>), dim3(grid), dim3(kStep2BS), 0, st, a);
+    md->ppar ^= 1;
+    md->vpar ^= 1;
+    return hipGetLastError();
+}
+
+// Ordinary steps that the next launch can take together: up to three (with
+// three-step tiles) or two, fewer when `avail` steps remain or a
+// coarse-graining event falls on one of them.
+int fuse_len(const lj_md* md, int avail, bool check_events);
+
 // `count` ordinary steps (no coarse-graining event), two per launch where the
 // handle allows it.
 hipError_t launch_plain_steps(lj_md* md, hipStream_t st, int count) {
     hipError_t e = hipSuccess;
     while (count > 0 && e == hipSuccess) {
-        if (md->two_step && count >= 2) {
-            e = launch_step2(md, st);
-            count -= 2;
-        } else {
-            e = launch_step(md, st, false, false);
-            count -= 1;
-        }
+        const int n = fuse_len(md, count, false);
+        e = n == 3 ? launch_step3(md, st) : (n == 2 ? launch_step2(md, st) : launch_step(md, st, false, false));
+        count -= n;
     }
     return e;
 }
@@ -1897,8 +2024,8 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     if (md->two_step)
         hipLaunchKernelGGL(k_pair_build, dim3(md->npt), dim3(256), 0, st, (const int*)md->cs,
                            (const RepDev*)md->d_reps, (const int*)md->d_ptrep, (const short*)md->nbl,
-                           (const unsigned char*)md->nbc, S, md->maxnb, md->plist, md->pcnt, md->tlist, md->tcnt,
-                           md->d_err);
+                           (const unsigned char*)md->nbc, S, md->maxnb, md->rings, md->plist, md->pcnt, md->tlist,
+                           md->tcnt, md->d_err);
     md->ppar ^= 1;
     md->opar ^= 1;
     md->vpar ^= 1;
@@ -1908,6 +2035,13 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
 }
 
 bool event_due(lj_md* md, long long t_after) { return md->cg_on && (t_after % md->s_cg) == 0; }
+
+int fuse_len(const lj_md* md, int avail, bool check_events) {
+    const int mx = md->three_step ? 3 : (md->two_step ? 2 : 1);
+    int n = 1;
+    while (n < mx && n < avail && !(check_events && event_due(const_cast<lj_md*>(md), md->cg_t + n + 1))) ++n;
+    return n;
+}
 
 // One MD step launched eagerly (rebuild first if due).
 hipError_t eager_step(lj_md* md, hipStream_t st) {
@@ -1951,9 +2085,9 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
         hipError_t e = launch_rebuild(md, md->cap);
         for (int j = 0; j < md->K && e == hipSuccess;) {
             const bool ev = event_due(md, md->cg_t + 1);
-            const bool pair = md->two_step && !ev && j + 1 < md->K && !event_due(md, md->cg_t + 2);
-            const int n = pair ? 2 : 1;
-            e = pair ? launch_step2(md, md->cap) : launch_step(md, md->cap, false, ev);
+            const int n = ev ? 1 : fuse_len(md, md->K - j, true);
+            e = n == 3 ? launch_step3(md, md->cap)
+                       : (n == 2 ? launch_step2(md, md->cap) : launch_step(md, md->cap, false, ev));
             md->since_rebuild += n;
             if (md->cg_on) {
                 md->cg_t += n;
@@ -2011,7 +2145,7 @@ mdlg_status check_params(const lj_params& p, int r) {
     if (p.step_kernel < 0 || p.step_kernel > 3) return bad("step_kernel must be 0, 1, 2 or 3");
     if (p.gather_batch != 0 && p.gather_batch != 4 && p.gather_batch != 8 && p.gather_batch != 16)
         return bad("gather_batch must be 0, 4, 8 or 16");
-    if (p.fuse_steps < 0 || p.fuse_steps > 2) return bad("fuse_steps must be 0, 1 or 2");
+    if (p.fuse_steps < 0 || p.fuse_steps > 3) return bad("fuse_steps must be 0, 1, 2 or 3");
     return MDLG_OK;
 }
 
@@ -2131,33 +2265,42 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     }
     md->TT = (int)ttiles;
     md->nscan = (md->C + kScanTile - 1) / kScanTile;
-    // two-step tiles: about kPairTarget staged particles on average (owned and
-    // two rings), so that one block of kStep2BS threads advances a tile in
-    // about one pass per step; two rings of distinct cells need nc >= pT + 4
-    // (fuse_steps 0: only where tiles are at least kPairAutoT cells wide, so
-    // that the halo adds at most ~30% to the first step; 2: wherever the
-    // geometry allows)
+    // fused tiles: about kPairTarget3 staged particles on average with three
+    // rings (kPairTarget with two), so that one block of kStep2BS threads
+    // advances a tile in about one pass per step; k rings of distinct cells
+    // need nc >= pT + 2 k.  fuse_steps 0: three steps per launch where such
+    // tiles are at least kPairAutoT cells wide, else two where the two-ring
+    // tiles are (the rings then add at most ~45% and ~20% to the first step);
+    // 2: two steps wherever the geometry allows; 3: three wherever it allows,
+    // else two.
     md->two_step = md->variant == 3 && p[0].fuse_steps != 1;
-    const int tmin = p[0].fuse_steps == 2 ? 2 : kPairAutoT;
     {
-        long long pt = 0;
-        for (int r = 0; r < n_rep && md->two_step; ++r) {
-            RepDev& d = md->reps[r].d;
-            const double ppc = std::max((double)d.n / ((double)d.nc * d.nc), 1e-9);
-            int T = (int)std::floor(std::sqrt((double)kPairTarget / ppc)) - 4;
-            T = std::min(std::min(T, 32), d.nc - 4);
-            if (T < tmin) {
-                md->two_step = false;
-                break;
+        const int fs = p[0].fuse_steps;
+        const int tmin = fs >= 2 ? 2 : kPairAutoT;
+        auto tiles = [&](int rings, int target) {
+            long long pt = 0;
+            for (int r = 0; r < n_rep; ++r) {
+                RepDev& d = md->reps[r].d;
+                const double ppc = std::max((double)d.n / ((double)d.nc * d.nc), 1e-9);
+                int T = (int)std::floor(std::sqrt((double)target / ppc)) - 2 * rings;
+                T = std::min(std::min(T, 32), d.nc - 2 * rings);
+                if (T < tmin) return false;
+                d.pT = T;
+                d.pts = (d.nc + T - 1) / T;
+                d.pnt = d.pts * d.pts;
+                d.pt0 = (int)pt;
+                pt += d.pnt;
             }
-            d.pT = T;
-            d.pts = (d.nc + T - 1) / T;
-            d.pnt = d.pts * d.pts;
-            d.pt0 = (int)pt;
-            pt += d.pnt;
+            if (pt >= (1LL << 31) / kPairCap) return false;
+            md->npt = (int)pt;
+            md->rings = rings;
+            return true;
+        };
+        if (md->two_step) {
+            if (fs != 2 && tiles(3, kPairTarget3)) md->three_step = true;
+            else if (!tiles(2, kPairTarget)) md->two_step = false;
         }
-        if (pt >= (1LL << 31) / kPairCap) md->two_step = false;
-        md->npt = md->two_step ? (int)pt : 0;
+        if (!md->two_step) md->npt = 0;
     }
 
     auto A = [&](hipError_t e) { return e == hipSuccess; };
@@ -2419,9 +2562,9 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                     hipError_t e = hipSuccess;
                     for (int j = M; j < K && e == hipSuccess;) {
                         const bool ev = event_due(md, md->cg_t + 1);
-                        const bool pair = md->two_step && !ev && j + 1 < K && !event_due(md, md->cg_t + 2);
-                        const int n = pair ? 2 : 1;
-                        e = pair ? launch_step2(md, cs) : launch_step(md, cs, false, ev);
+                        const int n = ev ? 1 : fuse_len(md, K - j, true);
+                        e = n == 3 ? launch_step3(md, cs)
+                                   : (n == 2 ? launch_step2(md, cs) : launch_step(md, cs, false, ev));
                         if (md->cg_on) {
                             md->cg_t += n;
                             if (ev) md->events += 1;
@@ -2685,7 +2828,7 @@ extern "C" mdlg_status lj_md_info(const lj_md* md, lj_md_info_t* info) {
     info->cells_per_side = md->reps[0].d.nc;
     info->block_size = md->BS;
     info->cell_width = md->reps[0].d.w;
-    info->steps_per_launch = md->two_step ? 2 : 1;
+    info->steps_per_launch = md->three_step ? 3 : (md->two_step ? 2 : 1);
     info->reserved = 0;
     return MDLG_OK;
 }

@@ -357,23 +357,28 @@ def test_autotuner_returns_runnable_params(tmp_path, monkeypatch):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n,phi,kT,fuse,kw", [
-    (512, 0.0784, 20.0, 0, {}),
-    (2000, 0.4, 20.0, 2, {"block_size": 128}),
-    (700, 0.4, 20.0, 2, {"skin": 0.2, "rebuild_every": 3}),
-    (3000, 0.2, 1.0, 2, {"force_bits": 32}),
-    (20000, 0.0784, 20.0, 0, {"block_size": 512}),
+@pytest.mark.parametrize("n,phi,kT,fuse,spl,kw", [
+    (512, 0.0784, 20.0, 0, 3, {}),
+    (330, 0.07, 20.0, 0, 2, {}),                  # 20 cells a side: three-step tiles too narrow
+    (2000, 0.4, 20.0, 2, 2, {"block_size": 128}),
+    (2000, 0.4, 20.0, 3, 3, {"block_size": 128}),
+    (700, 0.4, 20.0, 2, 2, {"skin": 0.2, "rebuild_every": 3}),
+    (700, 0.4, 20.0, 3, 3, {"skin": 0.2, "rebuild_every": 3}),   # ragged tiles 6, 6, 1
+    (3000, 0.2, 1.0, 2, 2, {"force_bits": 32}),
+    (3000, 0.2, 1.0, 3, 3, {"force_bits": 32}),
+    (20000, 0.0784, 20.0, 0, 3, {"block_size": 512}),
+    (20000, 0.0784, 20.0, 2, 2, {}),
 ])
-def test_two_steps_per_launch_equal_one(n, phi, kT, fuse, kw):
-    """Two ordinary steps per launch (tiles with a staged halo) give the same
-    state, bit for bit, as one step per launch, with and without the fused
-    coarse-graining."""
-    print(f"two-step n={n} phi={phi} kT={kT} fuse={fuse} {kw}", flush=True)
+def test_fused_steps_per_launch_equal_one(n, phi, kT, fuse, spl, kw):
+    """Two or three ordinary steps per launch (tiles with a staged halo) give
+    the same state, bit for bit, as one step per launch, with and without the
+    fused coarse-graining."""
+    print(f"fused n={n} phi={phi} kT={kT} fuse={fuse} {kw}", flush=True)
     pos0, vel0, L = mi.initial_state(n, phi, kT, 5)
     out = []
     for f in (fuse, 1):
         sysm = gpu_system(pos0, vel0, L, fuse_steps=f, **kw)
-        assert sysm.info()["steps_per_launch"] == (2 if f != 1 else 1)
+        assert sysm.info()["steps_per_launch"] == (spl if f != 1 else 1)
         acc = sysm.attach_cg(max(7, int(L / 2.0)), 10)
         sysm.step(13)
         sysm.step(131)
@@ -384,15 +389,16 @@ def test_two_steps_per_launch_equal_one(n, phi, kT, fuse, kw):
         assert np.array_equal(x, y)
 
 
-def test_two_step_batched_replicas_equal_single():
+@pytest.mark.parametrize("fuse", [2, 3])
+def test_fused_batched_replicas_equal_single(fuse):
     import paper_2101_01160_amd as m
     specs = [(4096, 0.0784, 20.0), (1500, 0.4, 1.0), (9000, 0.2, 5.0)]
     states = [mi.initial_state(n, phi, kT, 11 + i) for i, (n, phi, kT) in enumerate(specs)]
     pos = np.concatenate([s[0] for s in states])
     vel = np.concatenate([s[1] for s in states])
-    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10, fuse_steps=2) for s in states]
+    params = [m.lj_params(s[0].shape[0], s[2], rebuild_every=10, fuse_steps=fuse) for s in states]
     batch = m.LJSystem(_cuda(pos), _cuda(vel), params=params)
-    assert batch.info()["steps_per_launch"] == 2
+    assert batch.info()["steps_per_launch"] == fuse
     # by default the dense replicas keep one step per launch
     dflt = m.LJSystem(_cuda(pos), _cuda(vel), params=[m.lj_params(p.n, p.box_l, rebuild_every=10) for p in params])
     assert dflt.info()["steps_per_launch"] == 1
