@@ -765,6 +765,7 @@ __device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsign
     for (int u = 0; u < kListU; ++u) kk[u] = list[off + u * stride];
 }
 
+// With use_first, the first kListU rows come from `first`.
 template <bool F32, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
@@ -970,6 +971,7 @@ constexpr int kPairAutoT = 16;     // smallest tile side (cells) of the default 
 constexpr int kPairTarget = 520;   // staged particles aimed at when choosing the tile side, two rings
 constexpr int kPairTarget3 = 640;  // the same with three rings
 constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248 for pT <= 32, three rings
+constexpr int kPairBuildBS = 256;  // threads of the tile list builder
 
 // Per tile, after the neighbour lists: the staged slots, as contiguous slot
 // ranges of the row-major cell order (owned rows; then ring 1: the rows above
@@ -981,13 +983,15 @@ constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248
 // neighbours of a ring-k particle lie within ring k + 1.  A tile that stages
 // more than kPairCap particles, or a neighbour outside that bound, raises
 // ERR_NLIST.
-__global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
+template <int BS>
+__global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
                                                     const int* __restrict__ ptrep, const short* __restrict__ nbl,
                                                     const unsigned char* __restrict__ nbc, int S, int maxnb, int rings,
                                                     int* __restrict__ plist, int4* __restrict__ pcnt,
                                                     unsigned short* __restrict__ tlist,
                                                     unsigned char* __restrict__ tcnt, int* err) {
-    __shared__ int sa[kPairSeg], sn[kPairSeg], so[kPairSeg + 1];
+    static_assert(kPairSeg <= 256 && BS % 256 == 0, "one segment per thread of each 256 threads");
+    __shared__ int sa[kPairSeg], sn[kPairSeg], so[kPairSeg + 1], skey[kPairSeg];
     const int t = blockIdx.x;
     const RepDev& R = reps[ptrep[t]];
     const int nc = R.nc, T = R.pT;
@@ -1042,17 +1046,28 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
             cb = 0;
         }
         const int base = R.cell0 + row * nc;
-        sa[q] = cs[base + ca];
-        sn[q] = cs[base + cb] - sa[q];
+        const int a0 = cs[base + ca], n0 = cs[base + cb] - a0;
+        sa[q] = a0;
+        sn[q] = n0;
+        skey[q] = n0 > 0 ? a0 : 0x7fffffff;  // non-empty segments have distinct first slots
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int q = 0; q < ns; ++q) {
-            so[q] = acc;
-            acc += sn[q];
+    // first staged index of each segment: exclusive prefix sums of the lengths
+    {
+        __shared__ int wsum[BS / 64];
+        const int q = threadIdx.x, lane = q & 63, wv = q >> 6;
+        const int v = q < ns ? sn[q] : 0;
+        int x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
-        so[ns] = acc;
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wv; ++w) off += wsum[w];
+        if (q < ns) so[q] = off + x - v;
+        if (q == BS - 1) so[ns] = off + x;  // the total (entries past ns are 0)
     }
     __syncthreads();
     // staged counts up to each ring: n[0] owned, n[k] owned and rings 1 .. k
@@ -1067,13 +1082,27 @@ __global__ __launch_bounds__(256) void k_pair_build(const int* __restrict__ cs, 
     if (threadIdx.x == 0) pcnt[t] = make_int4(own, n[1], n[2], tot);
     // non-empty segments sorted by first slot, for the staged index of a slot
     __shared__ int ss[kPairSeg], se[kPairSeg], sl[kPairSeg];
+    __shared__ int rk[BS / 256][256];
     __shared__ int nne;
     if (threadIdx.x == 0) nne = 0;
+    {
+        // rank of segment g among the non-empty ones, each 256 threads over a share of the others
+        constexpr int parts = BS / 256;
+        const int g = threadIdx.x & 255, part = threadIdx.x >> 8;
+        if (g < ns) {
+            const int kg = skey[g];
+            const int h0 = part * ns / parts, h1 = (part + 1) * ns / parts;
+            int rank = 0;
+#pragma unroll 8
+            for (int h = h0; h < h1; ++h) rank += skey[h] < kg ? 1 : 0;
+            rk[part][g] = rank;
+        }
+    }
     __syncthreads();
-    for (int g = threadIdx.x; g < ns; g += blockDim.x) {
+    for (int g = threadIdx.x; g < ns; g += BS) {
         if (sn[g] == 0) continue;
         int rank = 0;
-        for (int h = 0; h < ns; ++h) rank += (sn[h] > 0 && (sa[h] < sa[g] || (sa[h] == sa[g] && h < g))) ? 1 : 0;
+        for (int part = 0; part < BS / 256; ++part) rank += rk[part][g];
         ss[rank] = sa[g];
         se[rank] = sa[g] + sn[g];
         sl[rank] = so[g];
@@ -1145,15 +1174,34 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     __shared__ double2 vs[kPairCap];  // owned and ring-1 velocities
     __shared__ char2 wr[kPairCap];    // first-step image changes of owned particles
     const int t = xcd_tile(blockIdx.x, gridDim.x);
+    // a thread stages q = tid and tid + BS: their slots, and for the first its
+    // neighbour count and first list rows, all read before the tile's counts
+    // and replica arrive (every tile has kPairCap slot and count entries and
+    // maxnb rows; those past the counts are not used)
+    static_assert(BS <= kPairCap && kPairCap <= 2 * BS, "two staged particles per thread at most");
+    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
+    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
+    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    const unsigned int SL = (unsigned int)kPairCap;
+    const int qf = threadIdx.x;
+    const int s_first = list[qf];
+    const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
+    const int nn_first = tc[qf];
+    int pre[kListU];
+    list_rows(tl, (unsigned int)qf, SL, pre);
+    const int4 c = a.pcnt[t];
+    const int own = c.x, mid = c.y, tot = c.z;  // two steps stage the owned particles and rings 1, 2
     const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
     const RepDev& R = a.reps[r];
     const double L = R.L;
     const double invL = 1.0 / L;
-    const int4 c = a.pcnt[t];
-    const int own = c.x, mid = c.y, tot = c.z;  // two steps stage the owned particles and rings 1, 2
-    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
-    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
-    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    const double2* __restrict__ pin = a.pin;
+    // the four state loads in flight together (slot 0 stands in for unused ones)
+    const bool h0 = qf < tot, h1 = qf + BS < tot;
+    const double2 p0 = pin[h0 ? s_first : 0];
+    const double2 v0 = a.vel[qf < mid ? s_first : 0];
+    const double2 p1 = pin[h1 ? s_second : 0];
+    const double2 v1 = a.vel[qf + BS < mid ? s_second : 0];
     // A tile three cells or more from every box edge stages particles of cells
     // 1 .. nc - 2 only; they move less than a cell between rebuilds, so none
     // crosses the periodic boundary and separations need no image.
@@ -1161,23 +1209,10 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
     const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
     const bool interior = c0 >= 3 && r0 >= 3 && c1 <= nc - 3 && r1 <= nc - 3;
-    const double2* __restrict__ pin = a.pin;
-    const unsigned int SL = (unsigned int)kPairCap;
-    // the thread's first staged particle: its slot, and when it is owned or in
-    // ring 1 its neighbour count and first list rows, loaded with the positions
-    const int qf = threadIdx.x;
-    int s_first = 0, nn_first = 0;
-    int pre[kListU] = {0, 0, 0, 0};
-    if (qf < mid) {
-        nn_first = tc[qf];
-        list_rows(tl, (unsigned int)qf, SL, pre);
-    }
-    for (int q = threadIdx.x; q < tot; q += BS) {
-        const int s = list[q];
-        if (q == qf) s_first = s;
-        x0[q] = pin[s];
-        if (q < mid) vs[q] = a.vel[s];
-    }
+    if (h0) x0[qf] = p0;
+    if (qf < mid) vs[qf] = v0;
+    if (h1) x0[qf + BS] = p1;
+    if (qf + BS < mid) vs[qf + BS] = v1;
     __syncthreads();
     // first step: owned and ring-1 particles
     for (int q = threadIdx.x; q < mid; q += BS) {
@@ -1199,7 +1234,7 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     // second step: owned particles, the same lists into the first step's positions
     for (int q = threadIdx.x; q < own; q += BS) {
         const bool firstq = q == qf;
-        const int s = firstq ? s_first : list[q];
+        const int s = firstq ? s_first : s_second;
         const double2 p = x1[q];
         double2 v = vs[q];
         const int nn = firstq ? nn_first : tc[q];
@@ -1236,36 +1271,40 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
     __shared__ double2 vs[kPairCap];  // velocities of owned, rings 1 and 2
     __shared__ char2 wr[kPairCap];    // image changes of owned particles in steps 1 and 2
     const int t = xcd_tile(blockIdx.x, gridDim.x);
+    // staging as in k_step2_nlist: every load issued before the first wait
+    static_assert(BS <= kPairCap && kPairCap <= 2 * BS, "two staged particles per thread at most");
+    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
+    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
+    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    const unsigned int SL = (unsigned int)kPairCap;
+    const int qf = threadIdx.x;
+    const int s_first = list[qf];
+    const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
+    const int nn_first = tc[qf];
+    int pre[kListU];
+    list_rows(tl, (unsigned int)qf, SL, pre);
+    const int4 c = a.pcnt[t];
+    const int own = c.x, n1 = c.y, n2 = c.z, tot = c.w;
     const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
     const RepDev& R = a.reps[r];
     const double L = R.L;
     const double invL = 1.0 / L;
-    const int4 c = a.pcnt[t];
-    const int own = c.x, n1 = c.y, n2 = c.z, tot = c.w;
-    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
-    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
-    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    const double2* __restrict__ pin = a.pin;
+    const bool h0 = qf < tot, h1 = qf + BS < tot;
+    const double2 p0 = pin[h0 ? s_first : 0];
+    const double2 v0 = a.vel[qf < n2 ? s_first : 0];
+    const double2 p1 = pin[h1 ? s_second : 0];
+    const double2 v1 = a.vel[qf + BS < n2 ? s_second : 0];
     // staged cells 1 .. nc - 2 only (tiles four cells or more from every edge):
     // no staged particle crosses the periodic boundary between rebuilds
     const int nc = R.nc, T = R.pT, lt = t - R.pt0;
     const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
     const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
     const bool interior = c0 >= 4 && r0 >= 4 && c1 <= nc - 4 && r1 <= nc - 4;
-    const double2* __restrict__ pin = a.pin;
-    const unsigned int SL = (unsigned int)kPairCap;
-    const int qf = threadIdx.x;
-    int s_first = 0, nn_first = 0;
-    int pre[kListU] = {0, 0, 0, 0};
-    if (qf < n2) {
-        nn_first = tc[qf];
-        list_rows(tl, (unsigned int)qf, SL, pre);
-    }
-    for (int q = threadIdx.x; q < tot; q += BS) {
-        const int s = list[q];
-        if (q == qf) s_first = s;
-        xa[q] = pin[s];
-        if (q < n2) vs[q] = a.vel[s];
-    }
+    if (h0) xa[qf] = p0;
+    if (qf < n2) vs[qf] = v0;
+    if (h1) xa[qf + BS] = p1;
+    if (qf + BS < n2) vs[qf + BS] = v1;
     __syncthreads();
     // step 1: owned, rings 1 and 2, from xa into xb
     for (int q = threadIdx.x; q < n2; q += BS) {
@@ -1307,7 +1346,7 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
     // step 3: owned particles, from xa to global memory
     for (int q = threadIdx.x; q < own; q += BS) {
         const bool firstq = q == qf;
-        const int s = firstq ? s_first : list[q];
+        const int s = firstq ? s_first : s_second;
         const double2 p = xa[q];
         double2 v = vs[q];
         const int nn = firstq ? nn_first : tc[q];
@@ -1519,6 +1558,7 @@ __global__ void k_put_img(const int2* __restrict__ img_in, const int* __restrict
 // Exclusive scan of n ints (cnt) into out[0..n] (out[n] = total), three passes
 // over tiles of 4096 elements (1024 threads x 4).
 constexpr int kScanTile = 4096;
+constexpr int kScanDirect = 2048;  // up to this many tiles, two kernels (each tile sums the totals before it)
 
 __device__ __forceinline__ int block_excl_scan_1024(int v, int* lds, int& total) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1569,9 +1609,20 @@ __global__ __launch_bounds__(1024) void k_scan_top(int* bsum, int nb) {
     }
 }
 
+// With `sums`, boff holds the tile totals and each block adds up those of the
+// tiles before it (short scans, see kScanDirect); else boff holds the tile
+// offsets from k_scan_top.
 __global__ __launch_bounds__(1024) void k_scan_final(int* __restrict__ in, long long n,
-                                                     const int* __restrict__ boff, int* __restrict__ out) {
+                                                     const int* __restrict__ boff, int* __restrict__ out, int sums) {
     __shared__ int lds[32];
+    int tile_off;
+    if (sums) {
+        int part = 0;
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += 1024) part += boff[b];
+        block_excl_scan_1024(part, lds, tile_off);
+    } else {
+        tile_off = boff[blockIdx.x];
+    }
     const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
     int v[4];
     int s = 0;
@@ -1581,7 +1632,7 @@ __global__ __launch_bounds__(1024) void k_scan_final(int* __restrict__ in, long 
         s += v[j];
     }
     int total;
-    int ex = block_excl_scan_1024(s, lds, total) + boff[blockIdx.x];
+    int ex = block_excl_scan_1024(s, lds, total) + tile_off;
     for (int j = 0; j < 4; ++j) {
         if (base + j < n) out[base + j] = ex;
         ex += v[j];
@@ -1996,9 +2047,10 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     }
     const int nb = (C + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C, md->bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, md->bsum, nb);
+    const int direct = nb <= kScanDirect ? 1 : 0;
+    if (!direct) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, md->bsum, nb);
     hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, st, md->cnt, (long long)C, (const int*)md->bsum,
-                       md->cs);
+                       md->cs, direct);
     if (md->variant == 2)
         hipLaunchKernelGGL(k_tile_info, dim3((md->TT + 255) / 256), dim3(256), 0, st, (const int*)md->cs,
                            (const RepDev*)md->d_reps, (const int*)md->d_ttile_rep, md->TT, md->d_tinfo);
@@ -2022,7 +2074,7 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
                            (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
                            md->maxnb, md->nbl, md->nbc, md->pref, md->d_err);
     if (md->two_step)
-        hipLaunchKernelGGL(k_pair_build, dim3(md->npt), dim3(256), 0, st, (const int*)md->cs,
+        hipLaunchKernelGGL(k_pair_build<kPairBuildBS>, dim3(md->npt), dim3(kPairBuildBS), 0, st, (const int*)md->cs,
                            (const RepDev*)md->d_reps, (const int*)md->d_ptrep, (const short*)md->nbl,
                            (const unsigned char*)md->nbc, S, md->maxnb, md->rings, md->plist, md->pcnt, md->tlist,
                            md->tcnt, md->d_err);
