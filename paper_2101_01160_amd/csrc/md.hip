@@ -972,6 +972,8 @@ constexpr int kPairTarget = 520;   // staged particles aimed at when choosing th
 constexpr int kPairTarget3 = 640;  // the same with three rings
 constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248 for pT <= 32, three rings
 constexpr int kPairBuildBS = 256;  // threads of the tile list builder
+constexpr int kPairHashBits = 11;  // its slot table: 2048 buckets
+constexpr int kPairHash = 1 << kPairHashBits;
 
 // Per tile, after the neighbour lists: the staged slots, as contiguous slot
 // ranges of the row-major cell order (owned rows; then ring 1: the rows above
@@ -991,7 +993,7 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
                                                     unsigned short* __restrict__ tlist,
                                                     unsigned char* __restrict__ tcnt, int* err) {
     static_assert(kPairSeg <= 256 && BS % 256 == 0, "one segment per thread of each 256 threads");
-    __shared__ int sa[kPairSeg], sn[kPairSeg], so[kPairSeg + 1], skey[kPairSeg];
+    __shared__ int sa[kPairSeg], sn[kPairSeg], so[kPairSeg + 1];
     const int t = blockIdx.x;
     const RepDev& R = reps[ptrep[t]];
     const int nc = R.nc, T = R.pT;
@@ -1049,7 +1051,6 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         const int a0 = cs[base + ca], n0 = cs[base + cb] - a0;
         sa[q] = a0;
         sn[q] = n0;
-        skey[q] = n0 > 0 ? a0 : 0x7fffffff;  // non-empty segments have distinct first slots
     }
     __syncthreads();
     // first staged index of each segment: exclusive prefix sums of the lengths
@@ -1080,58 +1081,36 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         tot = kPairCap;
     }
     if (threadIdx.x == 0) pcnt[t] = make_int4(own, n[1], n[2], tot);
-    // non-empty segments sorted by first slot, for the staged index of a slot
-    __shared__ int ss[kPairSeg], se[kPairSeg], sl[kPairSeg];
-    __shared__ int rk[BS / 256][256];
-    __shared__ int nne;
-    if (threadIdx.x == 0) nne = 0;
-    {
-        // rank of segment g among the non-empty ones, each 256 threads over a share of the others
-        constexpr int parts = BS / 256;
-        const int g = threadIdx.x & 255, part = threadIdx.x >> 8;
-        if (g < ns) {
-            const int kg = skey[g];
-            const int h0 = part * ns / parts, h1 = (part + 1) * ns / parts;
-            int rank = 0;
-#pragma unroll 8
-            for (int h = h0; h < h1; ++h) rank += skey[h] < kg ? 1 : 0;
-            rk[part][g] = rank;
-        }
-    }
+    // staged slots: the thread of each segment writes its slots in staged
+    // order, to the tile's list and to an LDS table slot -> staged index (open
+    // addressing, kPairHash buckets for at most kPairCap keys, so a probe
+    // always reaches an empty bucket)
+    __shared__ int hkey[kPairHash];  // slot + 1; 0: empty
+    __shared__ unsigned short hval[kPairHash];
+    __shared__ int lq[kPairCap];  // slot of each staged index
+    for (int h = threadIdx.x; h < kPairHash; h += BS) hkey[h] = 0;
     __syncthreads();
-    for (int g = threadIdx.x; g < ns; g += BS) {
-        if (sn[g] == 0) continue;
-        int rank = 0;
-        for (int part = 0; part < BS / 256; ++part) rank += rk[part][g];
-        ss[rank] = sa[g];
-        se[rank] = sa[g] + sn[g];
-        sl[rank] = so[g];
-        atomicAdd(&nne, 1);
-    }
-    __syncthreads();
-    const int ne = nne;
+    auto bucket = [](int k) { return ((unsigned int)k * 2654435761u) >> (32 - kPairHashBits); };
     int* list = plist + (long long)t * kPairCap;
-    // segment of staged index q: the last g with so[g] <= q (among segments 0 .. ns - 1)
-    auto seg_of = [&](int q) {
-        int lo = 0, hi = ns - 1;
-        while (lo < hi) {
-            const int m = (lo + hi + 1) >> 1;
-            if (so[m] <= q) lo = m;
-            else hi = m - 1;
+    for (int g = threadIdx.x; g < ns; g += BS) {
+        const int q0 = so[g], a0 = sa[g];
+        const int m = min(sn[g], kPairCap - q0);
+        for (int i = 0; i < m; ++i) {
+            const int q = q0 + i, slot = a0 + i;
+            lq[q] = slot;
+            list[q] = slot;
+            unsigned int h = bucket(slot);
+            while (atomicCAS(&hkey[h], 0, slot + 1) != 0) h = (h + 1) & (kPairHash - 1);
+            hval[h] = (unsigned short)q;
         }
-        return lo;
-    };
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-        const int g = seg_of(q);
-        list[q] = sa[g] + (q - so[g]);
     }
+    __syncthreads();
     // particles of every ring but the last: neighbour counts and lists as staged indices
     const int slot0 = R.slot0, nrep = R.n;
     unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
     const int listed = n[rings - 1];
     for (int q = threadIdx.x; q < listed; q += blockDim.x) {
-        const int g = seg_of(q);
-        const int s = sa[g] + (q - so[g]);
+        const int s = lq[q];
         const int nn = nbc[s];
         tcnt[(long long)t * kPairCap + q] = (unsigned char)nn;
         int ring = 0;
@@ -1148,15 +1127,10 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
                 int kr = (s - slot0) + rows[u];
                 kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
                 const int k = slot0 + kr;
-                // last sorted segment starting at or before k
-                int lo = 0, hi = ne - 1;
-                while (lo < hi) {
-                    const int m = (lo + hi + 1) >> 1;
-                    if (ss[m] <= k) lo = m;
-                    else hi = m - 1;
-                }
-                int loc = -1;
-                if (ne > 0 && ss[lo] <= k && k < se[lo]) loc = sl[lo] + (k - ss[lo]);
+                unsigned int h = bucket(k);
+                int key;
+                while ((key = hkey[h]) != k + 1 && key != 0) h = (h + 1) & (kPairHash - 1);
+                int loc = key == 0 ? -1 : (int)hval[h];
                 if (loc < 0 || loc >= lim) {
                     atomicOr(err, ERR_NLIST);
                     loc = 0;
