@@ -77,7 +77,7 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2_nlist_1M_phi0.0784.traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step3_nlist_1M_phi0.0784.traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01160_amd", "csrc", "md.hip")
 
 
@@ -87,18 +87,20 @@ def source_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(n):
+def measured_traffic(n, spl):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
     same counter reads for a plain copy of known size), or None when the
-    summary is missing, for another workload, or older than the kernel source."""
+    summary is missing, for another workload or kernel, or older than the
+    kernel source."""
     try:
         kv = {}
         for ln in open(TRAFFIC_FILE):
             if ":" in ln and not ln.startswith("#"):
                 k, v = ln.split(":", 1)
                 kv[k.strip()] = v.strip()
-        if kv.get("source_sha256") != source_sha256() or int(kv.get("n", -1)) != n:
+        if (kv.get("source_sha256") != source_sha256() or int(kv.get("n", -1)) != n
+                or int(kv.get("steps_per_launch", -1)) != spl):
             return None
         fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"]) * 1024.0
         write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]) * 1024.0
@@ -209,7 +211,7 @@ def main():
     launch_ms = spl * t_step
     launch_bytes = spl * STEP_BYTES * n
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(n) if args.force_bits == 64 and args.step_kernel in (0, 3) else None
+    traffic = measured_traffic(n, spl) if args.force_bits == 64 and args.step_kernel in (0, 3) else None
     cg_extra_ms = max(t_cg - t_step, 1e-9) if kcnt[1] else float("nan")
 
     counts = acc.counts.cpu().numpy()[0]
