@@ -748,37 +748,41 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
 
 // Pair force on a particle at p from the nn entries of its neighbour list
 // (entry j at list[off + j * stride]); fetch(entry) returns the neighbour's
-// position.  Four entries per pass: four independent index loads, then four
+// position.  kListU entries per pass: their index loads, then their
 // position loads, then the arithmetic (entries past the list are masked).
+// Two per pass leave fewer masked slots than four: the lanes of a wave run as
+// many passes as the longest list among them.
 // Without `interior` every separation goes through the minimum image, which
 // leaves separations below L/2 unchanged bit for bit.
 // Neighbour-list entries are read U rows at a time.  The list has maxnb rows,
 // a multiple of U, so rows j0 .. j0 + U - 1 exist whenever j0 < nn: they are
 // loaded without waiting for the count nn, and entries past nn are replaced
 // by 0 (a valid index) before they are used as one.
-constexpr int kListU = 4;
+constexpr int kListU = 2;
+constexpr int kListPre = 2 * kListU;  // rows loaded ahead for a thread's first particle (maxnb >= 16)
 
-template <typename Entry>
+template <int N, typename Entry>
 __device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsigned int off, unsigned int stride,
-                                          int (&kk)[kListU]) {
+                                          int (&kk)[N]) {
 #pragma unroll
-    for (int u = 0; u < kListU; ++u) kk[u] = list[off + u * stride];
+    for (int u = 0; u < N; ++u) kk[u] = list[off + u * stride];
 }
 
-// With use_first, the first kListU rows come from `first`.
+// With use_first, the first kListPre rows come from `first`.
 template <bool F32, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
-                                            double& fy, const int (&first)[kListU], bool use_first) {
+                                            double& fy, const int (&first)[kListPre], bool use_first) {
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
     constexpr int U = kListU;
     for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
         int kk[U];
-        if (use_first && j0 == 0) {
+        if (use_first && j0 < kListPre) {
+            static_assert(kListPre == 2 * kListU, "two passes of rows loaded ahead");
 #pragma unroll
-            for (int u = 0; u < U; ++u) kk[u] = first[u];
+            for (int u = 0; u < U; ++u) kk[u] = j0 == 0 ? first[u] : first[U + u];
         } else {
             list_rows(list, off, stride, kk);
         }
@@ -829,7 +833,7 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
                                             double& fy) {
-    const int none[kListU] = {0, 0, 0, 0};
+    const int none[kListPre] = {};
     nlist_force<F32>(p, nn, list, off, stride, fetch, interior, L, invL, rc2, eps24, rc2f, eps24f, fx, fy, none,
                      false);
 }
@@ -1081,34 +1085,67 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         tot = kPairCap;
     }
     if (threadIdx.x == 0) pcnt[t] = make_int4(own, n[1], n[2], tot);
-    // staged slots: the thread of each segment writes its slots in staged
-    // order, to the tile's list and to an LDS table slot -> staged index (open
-    // addressing, kPairHash buckets for at most kPairCap keys, so a probe
-    // always reaches an empty bucket)
+    // Staged slots: segment order, then within each ring that has lists (all
+    // but the last) reordered by the particle's number of list-row groups
+    // (kListU rows each), most first, so that the lanes of a wave mostly run
+    // the same number of passes over their lists.  Within a group the order is
+    // that of LDS atomics: it moves staged indices, not results (each
+    // particle still sums its own list in list order).  An LDS table maps
+    // slot -> staged index (open addressing, kPairHash buckets for at most
+    // kPairCap keys, so a probe always reaches an empty bucket).
     __shared__ int hkey[kPairHash];  // slot + 1; 0: empty
     __shared__ unsigned short hval[kPairHash];
-    __shared__ int lq[kPairCap];  // slot of each staged index
+    __shared__ int lq[kPairCap];   // slot of each staged index
+    __shared__ int lq0[kPairCap];  // slots in segment order
+    __shared__ unsigned char gq[kPairCap];
+    constexpr int kGroups = 64;  // list-row groups 0 .. maxnb / kListU (maxnb <= 248)
+    __shared__ int gcnt[3][kGroups];
+    const int ng = maxnb / kListU + 1;
     for (int h = threadIdx.x; h < kPairHash; h += BS) hkey[h] = 0;
-    __syncthreads();
-    auto bucket = [](int k) { return ((unsigned int)k * 2654435761u) >> (32 - kPairHashBits); };
-    int* list = plist + (long long)t * kPairCap;
+    for (int e = threadIdx.x; e < 3 * kGroups; e += BS) gcnt[e / kGroups][e % kGroups] = 0;
     for (int g = threadIdx.x; g < ns; g += BS) {
         const int q0 = so[g], a0 = sa[g];
         const int m = min(sn[g], kPairCap - q0);
-        for (int i = 0; i < m; ++i) {
-            const int q = q0 + i, slot = a0 + i;
-            lq[q] = slot;
-            list[q] = slot;
-            unsigned int h = bucket(slot);
-            while (atomicCAS(&hkey[h], 0, slot + 1) != 0) h = (h + 1) & (kPairHash - 1);
-            hval[h] = (unsigned short)q;
+        for (int i = 0; i < m; ++i) lq0[q0 + i] = a0 + i;
+    }
+    __syncthreads();
+    const int listed = n[rings - 1];
+    auto ring_of = [&](int q) {
+        int r = 0;
+        while (q >= n[r]) ++r;
+        return r;
+    };
+    for (int q = threadIdx.x; q < listed; q += BS) {
+        const int g = (nbc[lq0[q]] + kListU - 1) / kListU;
+        gq[q] = (unsigned char)g;
+        atomicAdd(&gcnt[ring_of(q)][g], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < rings) {  // first staged index of each (ring, group), most groups first
+        const int r = threadIdx.x;
+        int acc = r == 0 ? 0 : n[r - 1];
+        for (int g = ng - 1; g >= 0; --g) {
+            const int c = gcnt[r][g];
+            gcnt[r][g] = acc;
+            acc += c;
         }
+    }
+    __syncthreads();
+    auto bucket = [](int k) { return ((unsigned int)k * 2654435761u) >> (32 - kPairHashBits); };
+    int* list = plist + (long long)t * kPairCap;
+    for (int q = threadIdx.x; q < tot; q += BS) {
+        const int qn = q < listed ? atomicAdd(&gcnt[ring_of(q)][gq[q]], 1) : q;
+        const int slot = lq0[q];
+        lq[qn] = slot;
+        list[qn] = slot;
+        unsigned int h = bucket(slot);
+        while (atomicCAS(&hkey[h], 0, slot + 1) != 0) h = (h + 1) & (kPairHash - 1);
+        hval[h] = (unsigned short)qn;
     }
     __syncthreads();
     // particles of every ring but the last: neighbour counts and lists as staged indices
     const int slot0 = R.slot0, nrep = R.n;
     unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
-    const int listed = n[rings - 1];
     for (int q = threadIdx.x; q < listed; q += blockDim.x) {
         const int s = lq[q];
         const int nn = nbc[s];
@@ -1161,7 +1198,7 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     const int s_first = list[qf];
     const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
     const int nn_first = tc[qf];
-    int pre[kListU];
+    int pre[kListPre];
     list_rows(tl, (unsigned int)qf, SL, pre);
     const int4 c = a.pcnt[t];
     const int own = c.x, mid = c.y, tot = c.z;  // two steps stage the owned particles and rings 1, 2
@@ -1255,7 +1292,7 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
     const int s_first = list[qf];
     const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
     const int nn_first = tc[qf];
-    int pre[kListU];
+    int pre[kListPre];
     list_rows(tl, (unsigned int)qf, SL, pre);
     const int4 c = a.pcnt[t];
     const int own = c.x, n1 = c.y, n2 = c.z, tot = c.w;
@@ -2350,7 +2387,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             mean_max = std::max(mean_max, 3.14159265358979 * d.w * d.w * (double)d.n / (d.L * d.L));
         }
         md->maxnb = std::min(248, ((int)std::ceil(2.0 * mean_max + 16.0) + 7) / 8 * 8);
-        static_assert(248 % kListU == 0, "list rows are read kListU at a time");
+        static_assert(248 % kListU == 0 && kListPre <= 16, "list rows are read kListU at a time");
         for (int r = 0; r < n_rep; ++r) {
             // list entries are 16-bit slot offsets: a neighbour lies within about
             // three cell rows of a particle in cell order
