@@ -283,6 +283,28 @@ def test_one_million_particles_sampled(kw):
     torch.cuda.synchronize()
 
 
+def test_one_million_fused_equals_one_step():
+    """The benchmark's launch configuration (three ordinary steps per launch on
+    tiles of 19 cells, coarse-graining every 50 steps) against one step per
+    launch on N = 2^20: the same state and accumulators, bit for bit."""
+    import torch
+    n, lx, s_cg = 1 << 20, 1024, 50
+    pos0, vel0, L = mi.initial_state(n, 0.0784, 20.0, 0)
+    out = []
+    for f in (0, 1):
+        print(f"one million fused={f}", flush=True)
+        sysm = gpu_system(pos0, vel0, L, fuse_steps=f)
+        assert sysm.info()["steps_per_launch"] == (3 if f == 0 else 1)
+        acc = sysm.attach_cg(lx, s_cg)
+        sysm.step(2 * s_cg + 7)
+        sysm.check()
+        out.append([_np(t) for t in sysm.state()] + [_np(acc.counts), _np(acc.moments)])
+        sysm.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_fp32_forces_track_fp64(kernel):
     # FP32 pair arithmetic: the trajectory stays within FP32 rounding of the FP64 oracle over 100 steps
