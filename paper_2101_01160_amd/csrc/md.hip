@@ -759,7 +759,8 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
 // a multiple of U, so rows j0 .. j0 + U - 1 exist whenever j0 < nn: they are
 // loaded without waiting for the count nn, and entries past nn are replaced
 // by 0 (a valid index) before they are used as one.
-constexpr int kListU = 2;
+constexpr int kListU = 2;              // fused kernels (lists ordered by length within a tile)
+constexpr int kListUOne = 4;           // one-step kernel (slot order: fewer, longer passes keep more loads in flight)
 constexpr int kListPre = 2 * kListU;  // rows loaded ahead for a thread's first particle (maxnb >= 16)
 
 template <int N, typename Entry>
@@ -770,20 +771,23 @@ __device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsign
 }
 
 // With use_first, the first kListPre rows come from `first`.
-template <bool F32, typename Entry, typename Fetch>
+template <bool F32, int U, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
                                             double& fy, const int (&first)[kListPre], bool use_first) {
+    static_assert(kListPre % U == 0, "whole passes of rows loaded ahead");
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
-    constexpr int U = kListU;
     for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
         int kk[U];
         if (use_first && j0 < kListPre) {
-            static_assert(kListPre == 2 * kListU, "two passes of rows loaded ahead");
 #pragma unroll
-            for (int u = 0; u < U; ++u) kk[u] = j0 == 0 ? first[u] : first[U + u];
+            for (int b = 0; b < kListPre / U; ++b)
+                if (j0 == b * U) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) kk[u] = first[b * U + u];
+                }
         } else {
             list_rows(list, off, stride, kk);
         }
@@ -829,13 +833,13 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
     fy = F32 ? (double)by : ay;
 }
 
-template <bool F32, typename Entry, typename Fetch>
+template <bool F32, int U, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
                                             double& fy) {
     const int none[kListPre] = {};
-    nlist_force<F32>(p, nn, list, off, stride, fetch, interior, L, invL, rc2, eps24, rc2f, eps24f, fx, fy, none,
+    nlist_force<F32, U>(p, nn, list, off, stride, fetch, interior, L, invL, rc2, eps24, rc2f, eps24f, fx, fy, none,
                      false);
 }
 
@@ -899,7 +903,7 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
         return pin[slot0 + kr];
     };
     double fx, fy;
-    nlist_force<F32>(p, nn, a.nbl, (unsigned int)s, (unsigned int)a.nslots, fetch, interior, L, invL, R.rc2, R.eps24,
+    nlist_force<F32, kListUOne>(p, nn, a.nbl, (unsigned int)s, (unsigned int)a.nslots, fetch, interior, L, invL, R.rc2, R.eps24,
                      R.rc2f, R.eps24f, fx, fy);
     int idx = MDLG_NQ;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
@@ -1234,7 +1238,7 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return x0[k]; };
         double fx, fy;
-        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
@@ -1252,7 +1256,7 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return x1[k]; };
         double fx, fy;
-        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
@@ -1326,7 +1330,7 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return xa[k]; };
         double fx, fy;
-        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
@@ -1343,7 +1347,7 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return xb[k]; };
         double fx, fy;
-        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
@@ -1364,7 +1368,7 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return xa[k]; };
         double fx, fy;
-        nlist_force<F32>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
+        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
@@ -2388,7 +2392,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             mean_max = std::max(mean_max, 3.14159265358979 * d.w * d.w * (double)d.n / (d.L * d.L));
         }
         md->maxnb = std::min(248, ((int)std::ceil(2.0 * mean_max + 16.0) + 7) / 8 * 8);
-        static_assert(248 % kListU == 0 && kListPre <= 16, "list rows are read kListU at a time");
+        static_assert(248 % kListU == 0 && 248 % kListUOne == 0 && kListPre <= 16, "list rows are read in whole passes");
         for (int r = 0; r < n_rep; ++r) {
             // list entries are 16-bit slot offsets: a neighbour lies within about
             // three cell rows of a particle in cell order
