@@ -2013,7 +2013,9 @@ hipError_t launch_step3(lj_md* md, hipStream_t st) {
 
 // Ordinary steps that the next launch can take together: up to three (with
 // three-step tiles) or two, fewer when `avail` steps remain or a
-// coarse-graining event falls on one of them.
+// coarse-graining event falls on one of them; a run of 3k + 1 ordinary steps
+// (k >= 1) starts with a two-step launch, so that it ends without a one-step
+// launch.
 int fuse_len(const lj_md* md, int avail, bool check_events);
 
 // `count` ordinary steps (no coarse-graining event), two per launch where the
@@ -2106,9 +2108,11 @@ bool event_due(lj_md* md, long long t_after) { return md->cg_on && (t_after % md
 
 int fuse_len(const lj_md* md, int avail, bool check_events) {
     const int mx = md->three_step ? 3 : (md->two_step ? 2 : 1);
-    int n = 1;
-    while (n < mx && n < avail && !(check_events && event_due(const_cast<lj_md*>(md), md->cg_t + n + 1))) ++n;
-    return n;
+    // m: ordinary steps before the next event (or the end of the run of steps)
+    int m = 1;
+    while (m < avail && !(check_events && event_due(const_cast<lj_md*>(md), md->cg_t + m + 1))) ++m;
+    if (mx == 3 && m % 3 == 1 && m >= 4) return 2;  // 2 + 2 + 3k: two two-step launches cost less than 3 + 1
+    return std::min(mx, m);
 }
 
 // One MD step launched eagerly (rebuild first if due).
