@@ -84,12 +84,12 @@ struct StepArgs {
     int stage_max;  // tile kernel: largest staged particle count (<= its LDS capacity)
     const short* __restrict__ nbl;          // neighbour lists [maxnb][S]: slot offsets
     const unsigned char* __restrict__ nbc;  // neighbour counts [S]
-    // two-step launches
-    double2* __restrict__ vout;                 // velocities written by the two-step kernel
-    const int* __restrict__ plist;              // [tiles][kPairCap]: owned, ring-1, ring-2 slots
-    const int4* __restrict__ pcnt;              // [tiles]: (owned, owned + ring 1, staged, 0)
+    // two- and three-step launches
+    double2* __restrict__ vout;                 // velocities written by the fused kernels
+    const int* __restrict__ plist;              // [tiles][kPairCap]: staged slots, owned then ring by ring
+    const int4* __restrict__ pcnt;              // [tiles]: staged counts up to the owned, ring 1, ring 2, all
     const unsigned short* __restrict__ tlist;   // [tiles][maxnb][kPairCap]: neighbours as staged indices
-    const unsigned char* __restrict__ tcnt;     // [tiles][kPairCap]: neighbour counts of owned and ring 1
+    const unsigned char* __restrict__ tcnt;     // [tiles][kPairCap]: neighbour counts of all rings but the last
     int maxnb;
     const int* __restrict__ ptile_rep;          // [tiles] replica
     int* __restrict__ cell_acc;
@@ -962,7 +962,7 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
 
 // Two consecutive ordinary steps per launch.  The box is cut into square tiles
 // of pT x pT cells; a block owns the particles of one tile.  Its staged set is
-// those particles (owned), then the particles of the one-cell ring around the
+// those particles (owned), then the particles of the ring of cells around the
 // tile (ring 1), then those of the next ring (ring 2).  Neighbour lists reach
 // one cell width, so ring 2 holds every neighbour of a ring-1 particle and
 // ring 1 every neighbour of an owned one.  The block loads the staged

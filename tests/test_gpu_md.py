@@ -425,15 +425,21 @@ def test_fused_batched_replicas_equal_single(fuse):
     dflt = m.LJSystem(_cuda(pos), _cuda(vel), params=[m.lj_params(p.n, p.box_l, rebuild_every=10) for p in params])
     assert dflt.info()["steps_per_launch"] == 1
     dflt.close()
+    bacc = batch.attach_cg(12, 7)
     batch.step(55)
     bpos = _np(batch.state()[0])
+    bcounts, bmom = _np(bacc.counts), _np(bacc.moments)
     batch.close()
     off = 0
-    for s, p in zip(states, params):
+    for r, (s, p) in enumerate(zip(states, params)):
         single = m.LJSystem(_cuda(s[0]), _cuda(s[1]), params=[m.lj_params(p.n, p.box_l, rebuild_every=10,
                                                                            fuse_steps=1)])
+        sacc = single.attach_cg(12, 7)
         single.step(55)
         assert np.array_equal(_np(single.state()[0]), bpos[off:off + p.n])
+        # coarse-graining of each replica: counts exact, moments to their rounding
+        assert np.array_equal(_np(sacc.counts)[0], bcounts[r])
+        np.testing.assert_allclose(bmom[r], _np(sacc.moments)[0], rtol=1e-13, atol=0)
         off += p.n
         single.close()
 
