@@ -43,7 +43,7 @@ __constant__ VelLut d_lut = kLut;
 
 constexpr int kPad = 512;  // slot padding of each replica (largest block size)
 
-enum : int { ERR_NONFINITE = 1, ERR_SKIN = 2, ERR_NLIST = 4 };
+enum : int { ERR_NONFINITE = 1, ERR_SKIN = 2, ERR_NLIST = 4, ERR_TILE = 8 };
 
 struct RepDev {
     double L, halfL, inv_w, w, skin_half;
@@ -992,8 +992,8 @@ constexpr int kPairHash = 1 << kPairHashBits;
 // but the last their neighbour counts and lists as staged indices,
 // [tile][row j][staged index q].  Neighbour lists reach one cell, so the
 // neighbours of a ring-k particle lie within ring k + 1.  A tile that stages
-// more than kPairCap particles, or a neighbour outside that bound, raises
-// ERR_NLIST.
+// more than kPairCap particles raises ERR_TILE, a neighbour outside that
+// bound ERR_NLIST.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
                                                     const int* __restrict__ ptrep, const short* __restrict__ nbl,
@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     const int own = n[0];
     int tot = so[ns];
     if (tot > kPairCap) {
-        if (threadIdx.x == 0) atomicOr(err, ERR_NLIST);
+        if (threadIdx.x == 0) atomicOr(err, ERR_TILE);
         tot = kPairCap;
     }
     if (threadIdx.x == 0) pcnt[t] = make_int4(own, n[1], n[2], tot);
@@ -2227,8 +2227,12 @@ mdlg_status sync_check(lj_md* md, hipStream_t st) {
     MDLG_HIP(hipMemcpy(&err, md->d_err, sizeof(int), hipMemcpyDeviceToHost));
     if (err) {
         md->broken = true;
-        if (err & ERR_NONFINITE) return fail(MDLG_ENONFINITE, "non-finite position or velocity on the device");
+        // capacity first: an overflow leaves forces incomplete, which can end in non-finite values
+        if (err & ERR_TILE)
+            return fail(MDLG_ECAPACITY, "a fused-step tile staged more than 768 particles (the particles clustered "
+                                        "since the tiles were sized); use fuse_steps 1");
         if (err & ERR_NLIST) return fail(MDLG_ECAPACITY, "a neighbour list overflowed its capacity");
+        if (err & ERR_NONFINITE) return fail(MDLG_ENONFINITE, "non-finite position or velocity on the device");
         return fail(MDLG_ESKIN, "a particle drifted beyond the cell-list skin between rebuilds; lower rebuild_every or raise skin");
     }
     return MDLG_OK;

@@ -411,6 +411,27 @@ def test_fused_steps_per_launch_equal_one(n, phi, kT, fuse, spl, kw):
         assert np.array_equal(x, y)
 
 
+def test_clustered_tile_overflow_is_reported():
+    """A cluster at liquid-like density in a dilute box stages more particles
+    than a three-ring tile holds: the run stops with MDLG_ECAPACITY naming the
+    tile (the kernels cap what they stage and flag it)."""
+    import paper_2101_01160_amd as m
+    n, L, a = 2000, 200.0, 1.5
+    g = np.arange(-40, 41) * a
+    pts = np.stack(np.meshgrid(g, g), axis=-1).reshape(-1, 2)
+    pts = pts[np.argsort((pts ** 2).sum(axis=1), kind="stable")][:n] + L / 2
+    rng = np.random.default_rng(3)
+    vel = rng.normal(0.0, 1.0, (n, 2))
+    vel -= vel.mean(axis=0)
+    print("clustered tile overflow", flush=True)
+    sysm = gpu_system(pts, vel, L, fuse_steps=3)
+    assert sysm.info()["steps_per_launch"] == 3
+    with pytest.raises(m.MDLGError, match="tile"):
+        sysm.step(10)
+        sysm.check()
+    sysm.close()
+
+
 @pytest.mark.parametrize("fuse", [2, 3])
 def test_fused_batched_replicas_equal_single(fuse):
     import paper_2101_01160_amd as m
