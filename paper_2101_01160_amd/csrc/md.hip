@@ -846,7 +846,7 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
 // Velocity-Verlet update with the force at the current position: complete
 // the half-step velocity (not on the first step, whose velocity is a full-step
 // one), kick, drift, wrap into [0, L) with the image change in (wx, wy).
-template <bool FIRST>
+template <bool FIRST, bool WRAP = true>
 __device__ __forceinline__ double2 vv_update(double2 p, double2& v, double fx, double fy, double dt, double hdt,
                                              double L, int& wx, int& wy) {
     if (!FIRST) {
@@ -860,6 +860,7 @@ __device__ __forceinline__ double2 vv_update(double2 p, double2& v, double fx, d
     pn.y = p.y + dt * v.y;
     wx = 0;
     wy = 0;
+    if (!WRAP) return pn;  // the caller knows that no particle reaches the box edge
     if (pn.x >= L) { pn.x -= L; wx = 1; }
     else if (pn.x < 0.0) { pn.x += L; wx = -1; if (pn.x >= L) { pn.x = 0.0; wx = 0; } }
     if (pn.y >= L) { pn.y -= L; wy = 1; }
@@ -1220,7 +1221,8 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
     const double2 v1 = a.vel[qf + BS < mid ? s_second : 0];
     // A tile three cells or more from every box edge stages particles of cells
     // 1 .. nc - 2 only; they move less than a cell between rebuilds, so none
-    // crosses the periodic boundary and separations need no image.
+    // crosses the periodic boundary: separations need no image, positions no
+    // wrap and images no update.
     const int nc = R.nc, T = R.pT, lt = t - R.pt0;
     const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
     const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
@@ -1241,10 +1243,11 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
         nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
-        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
         x1[q] = pn;
         vs[q] = v;
-        if (q < own) wr[q] = make_char2((signed char)wx, (signed char)wy);
+        if (q < own && !interior) wr[q] = make_char2((signed char)wx, (signed char)wy);
     }
     __syncthreads();
     // second step: owned particles, the same lists into the first step's positions
@@ -1259,10 +1262,13 @@ __global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
         nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
-        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        const char2 w1 = wr[q];
-        wx += w1.x;
-        wy += w1.y;
+        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        if (!interior) {
+            const char2 w1 = wr[q];
+            wx += w1.x;
+            wy += w1.y;
+        }
         if (wx | wy) {
             int2 im = a.img[s];
             im.x += wx;
@@ -1312,7 +1318,8 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
     const double2 p1 = pin[h1 ? s_second : 0];
     const double2 v1 = a.vel[qf + BS < n2 ? s_second : 0];
     // staged cells 1 .. nc - 2 only (tiles four cells or more from every edge):
-    // no staged particle crosses the periodic boundary between rebuilds
+    // no staged particle crosses the periodic boundary between rebuilds (no
+    // image, no wrap, no image update)
     const int nc = R.nc, T = R.pT, lt = t - R.pt0;
     const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
     const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
@@ -1333,10 +1340,11 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
         nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
-        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
         xb[q] = pn;
         vs[q] = v;
-        if (q < own) wr[q] = make_char2((signed char)wx, (signed char)wy);
+        if (q < own && !interior) wr[q] = make_char2((signed char)wx, (signed char)wy);
     }
     __syncthreads();
     // step 2: owned and ring 1, from xb into xa (every read of xa is done)
@@ -1350,10 +1358,11 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
         nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
-        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
         xa[q] = pn;
         vs[q] = v;
-        if (q < own) {
+        if (q < own && !interior) {
             const char2 w = wr[q];
             wr[q] = make_char2((signed char)(w.x + wx), (signed char)(w.y + wy));
         }
@@ -1371,10 +1380,13 @@ __global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
         nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
                          fx, fy, pre, firstq);
         int wx, wy;
-        const double2 pn = vv_update<false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        const char2 w1 = wr[q];
-        wx += w1.x;
-        wy += w1.y;
+        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        if (!interior) {
+            const char2 w1 = wr[q];
+            wx += w1.x;
+            wy += w1.y;
+        }
         if (wx | wy) {
             int2 im = a.img[s];
             im.x += wx;
