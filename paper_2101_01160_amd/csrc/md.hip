@@ -804,10 +804,9 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
                 dx = min_image_rint(dx, L, invL);
                 dy = min_image_rint(dy, L, invL);
             }
-            if (!valid) {
-                dx = L;  // far away: no force
-                dy = L;
-            }
+            // entries past the list (index 0: any staged particle, or the particle
+            // itself) are computed and then dropped with the cutoff test; a zero
+            // separation gives a NaN there, which the select discards
             if (F32) {
                 const float fdx = (float)dx, fdy = (float)dy;
                 const float r2 = fdx * fdx + fdy * fdy;
@@ -815,7 +814,7 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
                 const float ir2n = ir2 * (2.0f - r2 * ir2);
                 const float ir6 = ir2n * ir2n * ir2n;
                 float fr = eps24f * ir6 * (2.0f * ir6 - 1.0f) * ir2n;
-                fr = r2 < rc2f ? fr : 0.0f;
+                fr = (valid && r2 < rc2f) ? fr : 0.0f;
                 bx += fr * fdx;
                 by += fr * fdy;
             } else {
@@ -823,7 +822,7 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
                 const double ir2 = recip(r2);
                 const double ir6 = ir2 * ir2 * ir2;
                 double fr = eps24 * ir6 * (2.0 * ir6 - 1.0) * ir2;
-                fr = r2 < rc2 ? fr : 0.0;
+                fr = (valid && r2 < rc2) ? fr : 0.0;
                 ax += fr * dx;
                 ay += fr * dy;
             }
