@@ -752,7 +752,7 @@ extern "C" mdlg_status mdlg_feq_surrogate(mdlg_mlp* m, const double* x, double a
     float gf[kOut];
     MDLG_HIP(hipMemcpyAsync(gf, m->g1, sizeof(gf), hipMemcpyDeviceToHost, st));
     MDLG_HIP(hipStreamSynchronize(st));
-    // the judge: the Poisson-WSG closed form at the drift (|u| cos, |u| sin)
+    // the guard: the Poisson-WSG closed form at the drift (|u| cos, |u| sin)
     const double u[2] = {x[3] * x[4], x[3] * x[5]};
     double gw[MDLG_NQ];
     s = mdlg_feq_wsg(a2, lambda, u, gw);

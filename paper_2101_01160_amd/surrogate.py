@@ -231,8 +231,8 @@ def evaluate(net: SurrogateMLP, data: SurrogateData, idx, tol=1e-3, with_guard=F
            "frac_below_tol": float(np.mean(err <= tol)), "n": int(len(idx))}
     if with_guard:
         w = wsg_table(data, idx)
-        judge = np.abs(g - w).max(axis=1)
-        fallback = judge > tol
+        dev_wsg = np.abs(g - w).max(axis=1)
+        fallback = dev_wsg > tol
         final = np.where(fallback[:, None], w, g)
         e_final = np.abs(final - data.G[idx]).max(axis=1)
         e_wsg = np.abs(w - data.G[idx]).max(axis=1)
