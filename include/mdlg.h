@@ -46,7 +46,7 @@ typedef int32_t mdlg_status;
 #define MDLG_EHIP (-3)        /* a HIP runtime call failed                       */
 #define MDLG_ENONFINITE (-4)  /* non-finite position or velocity on the device   */
 #define MDLG_ESKIN (-5)       /* a particle drifted past the cell-list skin      */
-#define MDLG_ENOTIMPL (-6)    /* feature not available in this build             */
+#define MDLG_ENOTIMPL (-6)    /* feature not available in this library           */
 #define MDLG_ECAPACITY (-7)   /* a neighbour list or a fused-step tile overflowed its capacity */
 
 #define MDLG_NQ 49            /* D2Q49 lattice velocities, |v_x|, |v_y| <= 3     */

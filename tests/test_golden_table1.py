@@ -1,4 +1,4 @@
-"""Table 1 of the paper (MD initialisation parameters) read as this build
+"""Table 1 of the paper (MD initialisation parameters) read as this library
 reads it: every row describes the same box, L = dx * lx = 1000 sigma (the
 5.5 / 180 row has dx = 1000/180 = 5.55..., printed rounded); the MD output
 frequency is the number of MD steps per coarse step, dt_cg / 1e-4; the total
