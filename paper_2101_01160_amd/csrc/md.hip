@@ -54,7 +54,7 @@ struct RepDev {
     int tile0, ntile;  // slot tiles (blocks of the block size) of this replica
     int ttile0, nttile;  // cell tiles of the step kernel: nc rows x tpr tiles of tw cells
     int tw, tpr;
-    // two-step tiles: pT x pT cells, pts per side, the first global index pt0
+    // fused tiles (two or three steps per launch): pT x pT cells, pts per side, the first global index pt0
     int pt0, pT, pts, pnt;
     // coarse-graining lattice
     int lx, pad_;
@@ -1823,7 +1823,7 @@ struct lj_md {
     bool two_step = false;
     bool three_step = false;          // also three ordinary steps per launch (implies two_step)
     int rings = 2;                    // cell rings staged per fused tile
-    int npt = 0;                      // two-step tiles
+    int npt = 0;                      // fused tiles
     int* d_ptrep = nullptr;           // [npt] replica
     int* plist = nullptr;             // [npt][kPairCap]
     int4* pcnt = nullptr;             // [npt]
