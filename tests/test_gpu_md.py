@@ -411,6 +411,36 @@ def test_fused_steps_per_launch_equal_one(n, phi, kT, fuse, spl, kw):
         assert np.array_equal(x, y)
 
 
+def test_paper_system_batch_fused_equals_one_step():
+    """The paper-regime launch configuration: four systems of N = 99,856 in
+    L = 1000 (phi = 0.0784, kT = 20) stepped as one batch, three steps per
+    launch, coarse-grained on Table 1's first lattice (250^2, 3911 MD steps):
+    the same states and counts, bit for bit, as one step per launch."""
+    import torch
+
+    import paper_2101_01160_amd as m
+    n, L = 99856, 1000.0
+    phi = n * np.pi / (4.0 * L * L)
+    states = [mi.initial_state(n, phi, 20.0, 40 + r) for r in range(4)]
+    pos = np.concatenate([s_[0] for s_ in states])
+    vel = np.concatenate([s_[1] for s_ in states])
+    out = []
+    for f in (0, 1):
+        print(f"paper batch fused={f}", flush=True)
+        params = [m.lj_params(n, states[r][2], fuse_steps=f) for r in range(4)]
+        b = m.LJSystem(_cuda(pos), _cuda(vel), params=params)
+        assert b.info()["steps_per_launch"] == (3 if f == 0 else 1)
+        acc = b.attach_cg([250] * 4, 391)
+        b.step(2 * 391 + 5)
+        b.check()
+        out.append([_np(t) for t in b.state()] + [_np(acc.counts)])
+        b.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+    assert out[0][3].sum() == 4 * n * 2
+    torch.cuda.synchronize()
+
+
 def test_clustered_tile_overflow_is_reported():
     """A cluster at liquid-like density in a dilute box stages more particles
     than a three-ring tile holds: the run stops with MDLG_ECAPACITY naming the
