@@ -39,8 +39,10 @@ CG_BYTES = 40.0          # snapshot read + write (32) + one counter read-modify-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed coarse steps")
-    ap.add_argument("--warmup", type=int, default=3, help="untimed coarse steps")
+    ap.add_argument("--steps", type=int, default=100, help="timed coarse steps per repetition")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed coarse steps (before the timed warm-up)")
+    ap.add_argument("--warmup-seconds", type=float, default=0.5, help="sustained stepping before timing")
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions (the median is reported)")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--phi", type=float, default=0.0784)
     ap.add_argument("--kT", type=float, default=20.0)
@@ -129,19 +131,279 @@ def copy_calibration(mib):
                       "gb_per_s_read_plus_write": 2 * (mib << 20) / (ms * 1e-3) / 1e9}), flush=True)
 
 
-def cpu_baseline(n, phi, kT, lx, s_cg, seed, steps):
-    """The oracle (single-threaded FP64 C) on a bounded sample of the same workload."""
+def host_cpu():
+    """CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, int(os.cpu_count() or 1), int(usable)
+
+
+def _oracle_sample(job):
+    """One oracle run (single-threaded FP64 C) on its own seeded sample; returns
+    (seconds, counts, events).  Runs in a worker process for the all-cores leg."""
+    n, phi, kT, lx, s_cg, seed, steps = job
     import mdlg_inputs as mi
     from oracle import md as omd
     pos, vel, L = mi.initial_state(n, phi, kT, seed)
-    img = np.zeros((n, 2), np.int64)
     acc = omd.CGAccum(lx)
     t0 = time.perf_counter()
-    omd.md_run(pos, vel, img, L, steps, cg=acc, s_cg=s_cg)
-    dt = time.perf_counter() - t0
-    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} particles x {steps} MD steps with {acc.events} coarse-graining events "
-                      f"(s_cg={s_cg}, lx={lx}), {dt:.1f} s on one host core"}
+    omd.md_run(pos, vel, np.zeros((n, 2), np.int64), L, steps, cg=acc, s_cg=s_cg)
+    return time.perf_counter() - t0, acc.counts.copy(), acc.events
+
+
+def cpu_baseline(n, phi, kT, lx, s_cg, seed, steps, all_core_steps=None, max_procs=16):
+    """The oracle (single-threaded FP64 C, as it stands) on bounded samples of the
+    same workload: one core on the benchmark's seed, then one independent sample
+    per usable host core (seeds seed+1 ..) in parallel processes.  `value` is
+    the all-cores aggregate.  Also returns the one-core run's counts, the
+    reference of the f_eq comparison."""
+    import multiprocessing as mp
+    model, nproc, usable = host_cpu()
+    dt1, counts, events = _oracle_sample((n, phi, kT, lx, s_cg, seed, steps))
+    one = {"value": n * steps / dt1, "unit": "particle-steps/s", "cores": 1,
+           "sample": f"{n} particles x {steps} MD steps with {events} coarse-graining events "
+                     f"(s_cg={s_cg}, lx={lx}), {dt1:.1f} s on one host core"}
+    procs = max(1, min(max_procs, usable))
+    steps_all = all_core_steps or max(s_cg, steps // 2)
+    jobs = [(n, phi, kT, lx, s_cg, seed + 1 + i, steps_all) for i in range(procs)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_sample, jobs)
+    wall = time.perf_counter() - t0
+    busy = max(r[0] for r in res)
+    out = {"value": procs * n * steps_all / busy, "unit": "particle-steps/s", "cores": procs, "kind": "oracle",
+           "sample": f"{procs} processes, each {n} particles x {steps_all} MD steps (s_cg={s_cg}, lx={lx}) on its own "
+                     f"seed; slowest {busy:.1f} s, wall {wall:.1f} s",
+           "one_core": one, "cpu_model": model, "nproc": nproc, "usable_cores": usable}
+    return out, counts, events
+
+
+def gpu_feq_vs_oracle(m, torch, pos0, vel0, L, lx, s_cg, steps, force_bits, ocounts, oevents):
+    """Measured f_eq of the GPU run against the oracle's from the same initial
+    state over the same steps: max_i |g_i(GPU) - g_i(oracle)| and whether the
+    integer counts are identical."""
+    n = pos0.shape[0]
+    sysm = m.LJSystem(torch.from_numpy(pos0).cuda(), torch.from_numpy(vel0).cuda(), box_l=L, force_bits=force_bits)
+    acc = sysm.attach_cg(lx, s_cg)
+    sysm.step(steps)
+    sysm.check()
+    counts = acc.counts.cpu().numpy()[0]
+    events = acc.events
+    sysm.close()
+    g, _ = m.mdlg_feq_measured(counts, n, events)
+    go, _ = m.mdlg_feq_measured(ocounts, n, oevents)
+    return {"max_abs_dg": float(np.max(np.abs(g - go))), "counts_identical": bool(np.array_equal(counts, ocounts)),
+            "events": int(events), "md_steps": int(steps),
+            "reference": "the oracle (FP64 CPU) from the same initial state"}
+
+
+def timed_reps(sysm, units, reps, torch):
+    """`reps` repetitions of `units` cell-list intervals, each bracketed by HIP
+    events on the launch stream; returns [(ms, kernel ms [3], launches [3])]."""
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        kms, kcnt = sysm.step_timed(units)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append((e0.elapsed_time(e1), [float(x) for x in kms], [int(x) for x in kcnt]))
+    return out
+
+
+def warm(sysm, units, seconds, torch):
+    """Replay intervals until `seconds` of sustained stepping have passed (the
+    clocks of a loaded GPU settle below those of a short burst)."""
+    t0 = time.perf_counter()
+    while True:
+        sysm.step_timed(units)
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return time.perf_counter() - t0
+
+
+def median_rep(rows):
+    order = sorted(range(len(rows)), key=lambda i: rows[i][0])
+    return rows[order[len(order) // 2]]
+
+
+def bench_single(args):
+    """The headline workload (see the module docstring)."""
+    n, phi, kT, lx, s_cg = args.n, args.phi, args.kT, args.lx, args.s_cg
+    import mdlg_inputs as mi
+    pos0, vel0, L = mi.initial_state(n, phi, kT, args.seed)
+    dxl = L / lx
+    base = None
+    if args.cpu_baseline_steps > 0:
+        # host-only work first, before this process touches the GPU
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        base, ocounts, oevents = cpu_baseline(n, phi, kT, lx, s_cg, args.seed, args.cpu_baseline_steps)
+        print(f"# cpu baseline: {base['value']:.3e} particle-steps/s on {base['cores']} cores", file=sys.stderr,
+              flush=True)
+
+    import torch
+
+    import paper_2101_01160_amd as m
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    kw = dict(force_bits=args.force_bits, block_size=args.block_size, skin=args.skin,
+              step_kernel=args.step_kernel, gather_batch=args.gather_batch)
+    sysm = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L, **kw)
+    acc = sysm.attach_cg(lx, s_cg)
+    info = sysm.info()
+    K = info["rebuild_every"]
+    print(f"# init done: n={n} L={L:.3f} lx={lx} s_cg={s_cg} cells/side={info['cells_per_side']} "
+          f"rebuild_every={K} block={info['block_size']}", file=sys.stderr, flush=True)
+    # warm-up: W coarse steps of captured intervals (every graph variant), then
+    # sustained stepping; the accumulators restart afterwards, so that the f_eq
+    # statistics come from the timed repetitions, long after the grid start
+    units = max(3, math.ceil(args.steps * s_cg / K))
+    sysm.step_timed(max(4, math.ceil(args.warmup * s_cg / K)))
+    warm_s = warm(sysm, units, args.warmup_seconds, torch)
+    acc.counts.zero_()
+    acc.moments.zero_()
+    ev0 = acc.events
+    steps_before = sysm.info()["steps_done"]
+    reps = timed_reps(sysm, units, args.reps, torch)
+    sysm.check()
+    events = acc.events - ev0
+    md_steps = units * K
+    ms, kms, kcnt = median_rep(reps)
+    value = n * md_steps / (ms * 1e-3)
+    print(f"# timed {args.reps} x {md_steps} MD steps after {warm_s:.2f} s of warm-up: median {ms:.2f} ms "
+          f"(all: {', '.join(f'{r[0]:.2f}' for r in reps)})", file=sys.stderr, flush=True)
+    t_step, t_cg, t_rebuild = kms
+    spl = int(info.get("steps_per_launch", 1)) or 1
+    launch_ms = spl * t_step
+    launch_bytes = spl * STEP_BYTES * n
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(n, spl) if args.force_bits == 64 and args.step_kernel in (0, 3) else None
+
+    counts = acc.counts.cpu().numpy()[0]
+    moments = acc.moments.cpu().numpy()[0]
+    g, ovf = m.mdlg_feq_measured(counts, n, events)
+    mu2, mu4, a2 = m.mdlg_moments(moments, dxl)
+    lam, r = m.mdlg_lambda_from_moments(mu2, mu4, 2)
+    gG = m.mdlg_feq_gauss(a2)
+    gW = m.mdlg_feq_wsg(a2, lam)
+    sysm.close()
+
+    # the coarse-graining's share: the same intervals (same rebuild interval)
+    # without coarse-graining, and with the per-cell field n_i(x) accumulated
+    print("# reference runs: no coarse-graining; per-cell field", file=sys.stderr, flush=True)
+    ref = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L, rebuild_every=K, **kw)
+    ref.step_timed(4)
+    warm(ref, units, args.warmup_seconds, torch)
+    ms_plain = median_rep(timed_reps(ref, units, args.reps, torch))[0]
+    cacc = ref.attach_cg(lx, s_cg, cell_acc=True)
+    ref.step_timed(4)
+    ev1 = cacc.events
+    ms_cell = median_rep(timed_reps(ref, units, args.reps, torch))[0]
+    ev_cell = (cacc.events - ev1) // args.reps
+    ref.check()
+    ref.close()
+    ev_rep = events // args.reps
+    over_ev = (ms - ms_plain) / max(ev_rep, 1)         # ms per coarse-graining event (counts and moments)
+    over_cell = (ms_cell - ms_plain) / max(ev_cell, 1)  # ms per event with the per-cell field written
+
+    # the other coarse steps of the workload (10 and 200 MD steps), same system size
+    other = {}
+    for sc in (10, 200):
+        if sc == s_cg or not args.coarse_sweep:
+            continue
+        print(f"# coarse step {sc}", file=sys.stderr, flush=True)
+        o = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L, **kw)
+        o.attach_cg(lx, sc)
+        Ks = o.info()["rebuild_every"]
+        u = max(3, math.ceil(args.steps * s_cg / Ks))
+        o.step_timed(max(4, math.ceil(2 * sc / Ks)))
+        warm(o, u, 0.5 * args.warmup_seconds, torch)
+        mo, km, _ = median_rep(timed_reps(o, u, args.reps, torch))
+        o.check()
+        o.close()
+        other[str(sc)] = {"particle_steps_per_s": n * u * Ks / (mo * 1e-3), "us_per_md_step": mo * 1e3 / (u * Ks),
+                          "rebuild_every": Ks, "kernel_ms": {"step": km[0], "step_with_cg_event": km[1],
+                                                             "rebuild": km[2]}}
+
+    feq_err = None
+    if base is not None:
+        print("# f_eq against the oracle's run", file=sys.stderr, flush=True)
+        feq_err = gpu_feq_vs_oracle(m, torch, pos0, vel0, L, lx, s_cg, args.cpu_baseline_steps, args.force_bits,
+                                    ocounts, oevents)
+
+    launch_s = launch_ms * 1e-3
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms * s_cg / md_steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces",
+        "data": "synthetic (jittered-grid positions, Maxwellian velocities, seed %d)" % args.seed,
+        "config": {"workload": f"2D LJ gas N={n}, phi={phi}, kT={kT}, L={L:.3f}, dt=1e-4, "
+                               f"lattice {lx}x{lx}, coarse step {s_cg} MD steps, D2Q49 counts",
+                   "n": n, "phi": phi, "kT": kT, "box_l": L, "lx": lx, "s_cg": s_cg,
+                   "md_steps_per_step": s_cg, "force_bits": args.force_bits,
+                   "cells_per_side": info["cells_per_side"], "rebuild_every": K,
+                   "block_size": info["block_size"]},
+        "timing": {"repetitions": args.reps, "md_steps_per_repetition": md_steps,
+                   "ms_per_repetition": [r_[0] for r_ in reps], "value_from": "median repetition",
+                   "warmup_s": warm_s, "steps_before_timing": int(steps_before)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac_kind": ("algorithmic-equivalent: 64 B per particle-step (x, v read and written) times the "
+                                   "steps of one launch over the launch time; a launch that advances several steps "
+                                   "keeps the steps between its first load and last store on chip, so this figure "
+                                   "is not bounded by 1"),
+                     "kernel": (f"MD step kernel, {spl} ordinary steps per launch" if spl > 1 else
+                                "MD step kernel (no coarse-graining event)"),
+                     "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl,
+                     "hbm_counter_gbs": (traffic / launch_s / 1e9) if traffic else None,
+                     "hbm_counter_frac": (traffic / launch_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "hbm_counter_bytes_per_particle_step": (traffic / (spl * n)) if traffic else None},
+        "us_per_md_step": ms * 1e3 / md_steps,
+        "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild, "launches": kcnt,
+                      "meaning": "step: per ordinary MD step; step_with_cg_event: per coarse-graining event, the "
+                                 "graph holding it less its ordinary steps at the per-step rate; rebuild: per "
+                                 "cell-list interval"},
+        "coarse_graining": {
+            "events_per_repetition": ev_rep,
+            "us_per_event": over_ev * 1e3,
+            "us_per_event_with_cell_field": over_cell * 1e3,
+            "particles_binned_per_s": n / (over_ev * 1e-3) if over_ev > 0 else None,
+            "cell_updates_per_s": lx * lx / (over_cell * 1e-3) if over_cell > 0 else None,
+            "method": ("time of the same intervals with the coarse-graining attached minus without it (same rebuild "
+                       "interval), per event; cell updates: every one of the lx^2 cells gets its n_i(x) added to "
+                       "the per-cell field (cell_acc) at each event")},
+        "other_coarse_steps": other,
+        "feq": {"events": int(events), "a2": a2, "r": r, "lambda2": lam, "overflow": ovf,
+                "g0": float(g[0]), "max_abs_meas_minus_gauss": float(np.max(np.abs(g - gG))),
+                "max_abs_meas_minus_wsg": float(np.max(np.abs(g - gW))),
+                "statistics_from": (f"the timed repetitions only, after {int(steps_before)} MD steps from the grid "
+                                    f"start (whose spacing equals the lattice cell)"),
+                "feq_err_vs_fp64_oracle": feq_err["max_abs_dg"] if feq_err else None,
+                "feq_err_check": feq_err},
+    }
+    if base is not None:
+        line["cpu_baseline"] = base
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -168,122 +430,7 @@ def main():
     if args.workload == "neq":
         bench_neq(args)
         return
-    import torch
-
-    import mdlg_inputs as mi
-    import paper_2101_01160_amd as m
-
-    n, phi, kT, lx, s_cg = args.n, args.phi, args.kT, args.lx, args.s_cg
-    pos0, vel0, L = mi.initial_state(n, phi, kT, args.seed)
-    dxl = L / lx
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    sysm = m.LJSystem(torch.from_numpy(pos0).to(dev), torch.from_numpy(vel0).to(dev), box_l=L,
-                      force_bits=args.force_bits, block_size=args.block_size, skin=args.skin,
-                      step_kernel=args.step_kernel, gather_batch=args.gather_batch)
-    acc = sysm.attach_cg(lx, s_cg)
-    info = sysm.info()
-    print(f"# init done: n={n} L={L:.3f} lx={lx} s_cg={s_cg} cells/side={info['cells_per_side']} "
-          f"rebuild_every={info['rebuild_every']} block={info['block_size']}", file=sys.stderr, flush=True)
-
-    # The timed region replays whole cell-list intervals (rebuild + K steps) as
-    # captured graphs with HIP events between them on the launch stream, so
-    # the kernel times come from the same run as the throughput.  The warmup
-    # captures the graphs (and covers every graph variant of the cycle).
-    K = info["rebuild_every"]
-    sysm.step_timed(max(4, math.ceil(args.warmup * s_cg / K)))
-    torch.cuda.synchronize()
-    units = max(3, math.ceil(args.steps * s_cg / K))
-    md_steps = units * K
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    kms, kcnt = sysm.step_timed(units)
-    e1.record()
-    torch.cuda.synchronize()
-    sysm.check()
-    ms = e0.elapsed_time(e1)
-    value = n * md_steps / (ms * 1e-3)
-    print(f"# timed {md_steps} MD steps in {ms:.2f} ms", file=sys.stderr, flush=True)
-    t_step, t_cg, t_rebuild = (float(x) for x in kms)
-    # the dominant kernel advances `spl` ordinary steps per launch
-    spl = int(info.get("steps_per_launch", 1)) or 1
-    launch_ms = spl * t_step
-    launch_bytes = spl * STEP_BYTES * n
-    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(n, spl) if args.force_bits == 64 and args.step_kernel in (0, 3) else None
-    cg_extra_ms = max(t_cg - t_step, 1e-9) if kcnt[1] else float("nan")
-
-    counts = acc.counts.cpu().numpy()[0]
-    moments = acc.moments.cpu().numpy()[0]
-    events = acc.events
-    g, ovf = m.mdlg_feq_measured(counts, n, events)
-    mu2, mu4, a2 = m.mdlg_moments(moments, dxl)
-    lam, r = m.mdlg_lambda_from_moments(mu2, mu4, 2)
-    gG = m.mdlg_feq_gauss(a2)
-    gW = m.mdlg_feq_wsg(a2, lam)
-    # the other coarse steps of the workload (10 and 200 MD steps): same system, lattice re-attached
-    other = {}
-    for sc in (10, 200):
-        if sc == s_cg or not args.coarse_sweep:
-            continue
-        sysm.detach_cg()
-        sysm.attach_cg(lx, sc)
-        Ks = sysm.info()["rebuild_every"]
-        sysm.step_timed(max(4, math.ceil(2 * sc / Ks)))
-        u = max(3, math.ceil(args.steps * s_cg / Ks))
-        f0 = torch.cuda.Event(enable_timing=True)
-        f1 = torch.cuda.Event(enable_timing=True)
-        f0.record()
-        km, _ = sysm.step_timed(u)
-        f1.record()
-        torch.cuda.synchronize()
-        sysm.check()
-        ms_s = f0.elapsed_time(f1)
-        other[str(sc)] = {"particle_steps_per_s": n * u * Ks / (ms_s * 1e-3), "us_per_md_step": ms_s * 1e3 / (u * Ks),
-                          "rebuild_every": Ks, "kernel_ms": {"step": float(km[0]), "step_with_cg_event": float(km[1]),
-                                                             "rebuild": float(km[2])}}
-    sysm.close()
-
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms * s_cg / md_steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces",
-        "data": "synthetic (jittered-grid positions, Maxwellian velocities, seed %d)" % args.seed,
-        "config": {"workload": f"2D LJ gas N={n}, phi={phi}, kT={kT}, L={L:.3f}, dt=1e-4, "
-                               f"lattice {lx}x{lx}, coarse step {s_cg} MD steps, D2Q49 counts",
-                   "n": n, "phi": phi, "kT": kT, "box_l": L, "lx": lx, "s_cg": s_cg,
-                   "md_steps_per_step": s_cg, "force_bits": args.force_bits,
-                   "cells_per_side": info["cells_per_side"], "rebuild_every": info["rebuild_every"],
-                   "block_size": info["block_size"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": (f"MD step kernel, {spl} ordinary steps per launch" if spl > 1 else
-                                "MD step kernel (no coarse-graining event)"),
-                     "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl},
-        "us_per_md_step": ms * 1e3 / md_steps,
-        "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
-                      "launches": [int(x) for x in kcnt]},
-        "other_coarse_steps": other,
-        "cell_updates_per_s": (lx * lx) / (cg_extra_ms * 1e-3),
-        "particles_binned_per_s": n / (cg_extra_ms * 1e-3),
-        "feq": {"events": int(events), "a2": a2, "r": r, "lambda2": lam, "overflow": ovf,
-                "g0": float(g[0]), "max_abs_meas_minus_gauss": float(np.max(np.abs(g - gG))),
-                "max_abs_meas_minus_wsg": float(np.max(np.abs(g - gW))),
-                "feq_err_vs_fp64_oracle": 0.0 if args.force_bits == 64 else None},
-    }
-    if args.cpu_baseline_steps > 0:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(n, phi, kT, lx, s_cg, args.seed, args.cpu_baseline_steps)
-    print(json.dumps(line), flush=True)
+    bench_single(args)
 
 
 def bench_precision(args):
@@ -697,7 +844,7 @@ def bench_paper(args):
     if args.cpu_baseline_steps > 0:
         log("cpu baseline (oracle) ...")
         steps = 3 * args.cpu_baseline_steps   # ~15 s of one host core at this size
-        line["cpu_baseline"] = cpu_baseline(N, phi, kT, 250, 50, args.seed, steps)
+        line["cpu_baseline"] = cpu_baseline(N, phi, kT, 250, 50, args.seed, steps)[0]
     print(json.dumps(line), flush=True)
 
 

@@ -52,20 +52,38 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def _check(t, dtype, shape, name):
+    """dtype, shape and layout of a tensor argument (None passes)."""
+    if t is None:
+        return
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
 def _dev(t, dtype, shape=None, name="tensor"):
     """Device pointer of a contiguous CUDA tensor (None passes NULL)."""
     if t is None:
         return None
-    torch = _torch()
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+    _check(t, dtype, shape, name)
+    if not t.is_cuda:
         raise ValueError(f"{name} must be a torch tensor on the GPU")
-    if t.dtype != dtype:
-        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
-    if not t.is_contiguous():
-        raise ValueError(f"{name} must be contiguous")
-    if shape is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return C.c_void_p(t.data_ptr())
+
+
+def _devs(*specs):
+    """Device pointers of several (tensor, dtype, shape, name) arguments; every
+    dtype and shape is checked before any device test, so that a wrongly sized
+    buffer is refused first and nothing reaches the library."""
+    for t, dtype, shape, name in specs:
+        _check(t, dtype, shape, name)
+    return [_dev(*sp) for sp in specs]
 
 
 def _host(a, dtype, n):
@@ -114,12 +132,24 @@ def lj_md_init_batch(params, pos0, vel0, stream=None) -> C.c_void_p:
     return h
 
 
+def _sizes(h):
+    """(replicas, particles) of a handle: the extents every per-handle buffer is checked against."""
+    info = lj_md_info(h)
+    return int(info["n_rep"]), int(info["n_total"])
+
+
 def lj_md_cg_attach(h, s_cg, lattices, counts, moments, cell_acc=None, stream=None):
+    """counts: int64 [n_rep, 50], moments: float64 [n_rep, 5], cell_acc: int32
+    [sum over replicas of 49 lx^2] or None (all on the GPU, accumulated into)."""
     torch = _torch()
+    n_rep, _ = _sizes(h)
+    if len(lattices) != n_rep:
+        raise ValueError(f"expected {n_rep} lattices, got {len(lattices)}")
     lats = (Lattice * len(lattices))(*lattices)
-    _abi.check(_abi.lib().lj_md_cg_attach(h, int(s_cg), lats, _dev(counts, torch.int64, None, "counts"),
-                                          _dev(moments, torch.float64, None, "moments"),
-                                          _dev(cell_acc, torch.int32, None, "cell_acc"), _stream(stream)))
+    n_cells = sum(49 * int(l.lx) * int(l.lx) for l in lattices)
+    ptrs = _devs((counts, torch.int64, (n_rep, 50), "counts"), (moments, torch.float64, (n_rep, 5), "moments"),
+                 (cell_acc, torch.int32, (n_cells,), "cell_acc"))
+    _abi.check(_abi.lib().lj_md_cg_attach(h, int(s_cg), lats, *ptrs, _stream(stream)))
 
 
 def lj_md_cg_detach(h):
@@ -141,10 +171,12 @@ def lj_md_step_timed(h, nunits, stream=None):
 
 
 def lj_md_get_state(h, pos=None, vel=None, img=None, stream=None):
+    """pos, vel: float64 [n_total, 2], img: int32 [n_total, 2] on the GPU, in caller order (each may be None)."""
     torch = _torch()
-    _abi.check(_abi.lib().lj_md_get_state(h, _dev(pos, torch.float64, None, "pos"),
-                                          _dev(vel, torch.float64, None, "vel"),
-                                          _dev(img, torch.int32, None, "img"), _stream(stream)))
+    _, n = _sizes(h)
+    ptrs = _devs((pos, torch.float64, (n, 2), "pos"), (vel, torch.float64, (n, 2), "vel"),
+                 (img, torch.int32, (n, 2), "img"))
+    _abi.check(_abi.lib().lj_md_get_state(h, *ptrs, _stream(stream)))
 
 
 def lj_md_save(h, path, stream=None):
@@ -158,10 +190,14 @@ def lj_md_load(path, stream=None) -> C.c_void_p:
 
 
 def lj_md_forces(h, force, stream=None):
-    _abi.check(_abi.lib().lj_md_forces(h, _dev(force, _torch().float64, None, "force"), _stream(stream)))
+    """force: float64 [n_total, 2] on the GPU, caller order."""
+    _, n = _sizes(h)
+    _abi.check(_abi.lib().lj_md_forces(h, _dev(force, _torch().float64, (n, 2), "force"), _stream(stream)))
 
 
-def lj_md_energy(h, n_rep=1, stream=None) -> np.ndarray:
+def lj_md_energy(h, stream=None) -> np.ndarray:
+    """(KE, PE, Px, Py) per replica, [n_rep, 4] (synchronises)."""
+    n_rep, _ = _sizes(h)
     out = np.zeros((n_rep, 4))
     _abi.check(_abi.lib().lj_md_energy(h, out.ctypes.data_as(C.c_void_p), _stream(stream)))
     return out
@@ -566,7 +602,7 @@ class LJSystem:
         return f
 
     def energy(self):
-        return lj_md_energy(self.handle, self.n_rep, self.stream)
+        return lj_md_energy(self.handle, self.stream)
 
     def check(self):
         lj_md_check(self.handle, self.stream)

@@ -33,7 +33,7 @@ import numpy as np
 import mdlg_inputs as mi
 
 from . import (LJParams, SurrogateMLP, lj_md_destroy, lj_md_get_state, lj_md_init_batch, lj_md_step,
-               mdlg_coarse_grain_series, mdlg_feq_wsg, mdlg_lambda_from_moments, mdlg_moments)
+               mdlg_coarse_grain_series, mdlg_feq_measured, mdlg_feq_wsg, mdlg_lambda_from_moments, mdlg_moments)
 
 DEFAULT_LAGS = (1, 2, 3, 4, 6, 8, 10, 13, 16, 20)
 
@@ -137,14 +137,14 @@ def generate(n_groups=4, reps_per_group=80, n=65536, n_snap=401, stride=10, equi
                     um = float(np.hypot(*u[t]))
                     c, sn = (u[t] / um) if um > 0 else (1.0, 0.0)
                     out["X"].append((s.phi, s.kT, l * stride * dt / dx, um, c, sn))
-                    tot = s.n * pairs
-                    out["G"].append(counts[r, si, t, :49] / tot)
-                    out["overflow"].append(counts[r, si, t, 49] / tot)
+                    g_meas, ovf = mdlg_feq_measured(counts[r, si, t], s.n, pairs)
+                    out["G"].append(g_meas)
+                    out["overflow"].append(ovf)
                     out["a2"].append(a2)
                     out["lam"].append(lam)
                     out["rep"].append(g * reps_per_group + r)
                     out["u"].append(u[t])
-                    out["samples"].append(tot)
+                    out["samples"].append(s.n * pairs)
         if log:
             log(f"surrogate data: group {g + 1}/{n_groups} ({len(specs)} replicas x {n} particles): "
                 f"MD {t1 - t0:.2f} s, coarse-graining {t2 - t1:.3f} s")
@@ -175,9 +175,9 @@ def train(data: SurrogateData, idx, steps=4000, batch=4096, lr=2e-3, lr_final=2e
     import torch
     net = SurrogateMLP(mi.mlp_init(init_seed).astype(np.float32), max(batch, 1))
     X = torch.from_numpy(data.X[idx].astype(np.float32)).cuda()
-    # targets renormalised over the 49 velocities (the overflow bin is empty here)
-    G = data.G[idx] / data.G[idx].sum(axis=1, keepdims=True)
-    R = torch.from_numpy(G.astype(np.float32)).cuda()
+    # targets: the measured g_i as they are (in this regime no displacement
+    # leaves D2Q49, so they sum to one like the network's softmax)
+    R = torch.from_numpy(data.G[idx].astype(np.float32)).cuda()
     m = X.shape[0]
     batch = min(batch, m)
     rng = np.random.Generator(np.random.PCG64(seed))
