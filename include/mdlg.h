@@ -262,6 +262,23 @@ mdlg_status mdlg_coarse_grain(const mdlg_lattice* lat, double box_l, int64_t n,
                               int64_t* counts, double* moments, int32_t* n_event, int32_t* cell_acc,
                               void* stream);
 
+/* mdlg_coarse_grain for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (counts and moments bitwise
+ * equal to mdlg_coarse_grain's); it calls no allocating routine.  Its moment
+ * partials live in a fixed device array of the library (5.2 MB, one copy per
+ * GPU, held until the process ends), which limits n to 2^25 = 33,554,432
+ * particles: larger n is rejected with MDLG_EINVAL before anything is
+ * launched.  The stream must belong to the current device.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from several threads) race and give wrong moments; calls on one
+ * stream are ordered and safe. */
+mdlg_status mdlg_coarse_grain_noalloc(const mdlg_lattice* lat, double box_l, int64_t n,
+                                      const double* pos_prev, const int32_t* img_prev, int64_t k_prev,
+                                      const double* pos_cur, const int32_t* img_cur, int64_t k_cur,
+                                      int64_t* counts, double* moments, int32_t* n_event,
+                                      int32_t* cell_acc, void* stream);
+
 /* Coarse-graining of a stored trajectory for many coarse-graining times and
  * lattice drifts in one pass (Eq.(n_i) for every snapshot pair).  The batch
  * holds n_rep replicas; replica r owns particles offsets[r] .. offsets[r+1]-1

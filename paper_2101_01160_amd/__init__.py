@@ -29,7 +29,7 @@ __all__ = [
     "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_save", "lj_md_load",
     "lj_md_destroy",
     "lj_md_autotune",
-    "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
+    "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "NOALLOC_MAX_N", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg", "mdlg_velocity_table", "mdlg_version",
     "mdlg_neq_mdlg", "mdlg_vacf", "mdlg_lambda_vacf", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
@@ -37,6 +37,7 @@ __all__ = [
 ]
 
 MLP_NPARAMS = _abi.MLP_NPARAMS
+NOALLOC_MAX_N = _abi.NOALLOC_MAX_N
 
 
 def _torch():
@@ -236,11 +237,15 @@ def lj_md_autotune(params, pos0, vel0, s_cg=0, lattices=None, use_cache=True, st
 # ------------------------------------------------------- coarse-graining ---
 
 def mdlg_coarse_grain(lx, box_l, pos_prev, pos_cur, counts, moments=None, img_prev=None, img_cur=None,
-                      k_prev=0, k_cur=1, u=(0.0, 0.0), n_event=None, cell_acc=None, stream=None):
+                      k_prev=0, k_cur=1, u=(0.0, 0.0), n_event=None, cell_acc=None, stream=None, noalloc=False):
+    """One coarse-graining event between two snapshots (see include/mdlg.h).
+    noalloc=True calls mdlg_coarse_grain_noalloc (no device allocation; at
+    most NOALLOC_MAX_N particles)."""
     torch = _torch()
     n = pos_prev.shape[0]
     lat = Lattice(lx=int(lx), reserved=0, u=(C.c_double * 2)(float(u[0]), float(u[1])))
-    _abi.check(_abi.lib().mdlg_coarse_grain(
+    fn = _abi.lib().mdlg_coarse_grain_noalloc if noalloc else _abi.lib().mdlg_coarse_grain
+    _abi.check(fn(
         C.byref(lat), float(box_l), int(n),
         _dev(pos_prev, torch.float64, (n, 2), "pos_prev"), _dev(img_prev, torch.int32, (n, 2), "img_prev"),
         int(k_prev),

@@ -21,7 +21,7 @@ EXPORTS = [
     "lj_md_init", "lj_md_init_batch", "lj_md_cg_attach", "lj_md_cg_detach", "lj_md_step", "lj_md_step_timed",
     "lj_md_get_state", "lj_md_forces", "lj_md_energy", "lj_md_check", "lj_md_info", "lj_md_save", "lj_md_load", "lj_md_destroy",
     "lj_md_autotune",
-    "mdlg_coarse_grain", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
+    "mdlg_coarse_grain", "mdlg_coarse_grain_noalloc", "mdlg_coarse_grain_series", "mdlg_feq_measured", "mdlg_moments", "mdlg_lambda_from_moments",
     "mdlg_feq_gauss", "mdlg_feq_wsg",
     "mdlg_neq_mdlg", "mdlg_vacf", "mdlg_lambda_vacf", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
@@ -30,6 +30,7 @@ EXPORTS = [
 
 MLP_NPARAMS = 145969
 HIST_MAX_BINS = 4094
+NOALLOC_MAX_N = 1 << 25  # particles of one mdlg_coarse_grain_noalloc call
 
 
 class LJParams(C.Structure):
@@ -123,6 +124,7 @@ def lib() -> C.CDLL:
         "lj_md_destroy": (None, [vp]),
         "lj_md_autotune": (i32, [i32, P(LJParams), vp, vp, i32, P(Lattice), i32, P(LJParams), P(dbl), vp]),
         "mdlg_coarse_grain": (i32, [P(Lattice), dbl, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]),
+        "mdlg_coarse_grain_noalloc": (i32, [P(Lattice), dbl, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]),
         "mdlg_coarse_grain_series": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]),
         "mdlg_feq_measured": (i32, [vp, i64, i64, i32, vp, P(dbl)]),
         "mdlg_moments": (i32, [vp, dbl, P(dbl), P(dbl), P(dbl)]),

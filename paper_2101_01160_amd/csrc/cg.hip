@@ -8,6 +8,8 @@
 // non-empty bin.  Displacement moments go through per-block partials and a
 // fixed-order final sum, so they are bitwise reproducible.
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "mdlg_internal.h"
 
@@ -127,27 +129,63 @@ __global__ void k_zero_i32(int* p, long long n) {
 
 using namespace mdlg;
 
-extern "C" mdlg_status mdlg_coarse_grain(const mdlg_lattice* lat, double box_l, int64_t n, const double* pos_prev,
-                                         const int32_t* img_prev, int64_t k_prev, const double* pos_cur,
-                                         const int32_t* img_cur, int64_t k_cur, int64_t* counts, double* moments,
-                                         int32_t* n_event, int32_t* cell_acc, void* stream) {
-    if (!lat || !counts) return fail(MDLG_EINVAL, "mdlg_coarse_grain: lat and counts are required");
-    if (n < 0) return fail(MDLG_EINVAL, "mdlg_coarse_grain: n must be >= 0");
-    if (n > 0 && (!pos_prev || !pos_cur)) return fail(MDLG_EINVAL, "mdlg_coarse_grain: positions are required");
-    if (lat->lx < 1 || lat->lx > 46340) return fail(MDLG_EINVAL, "mdlg_coarse_grain: lx must be in [1, 46340]");
-    if (!(box_l > 0.0) || !std::isfinite(box_l)) return fail(MDLG_EINVAL, "mdlg_coarse_grain: box_l must be > 0");
-    if (!std::isfinite(lat->u[0]) || !std::isfinite(lat->u[1]))
-        return fail(MDLG_EINVAL, "mdlg_coarse_grain: u must be finite");
-    hipStream_t st = (hipStream_t)stream;
+// Scratch of mdlg_coarse_grain_noalloc: the per-block moment partials (5
+// doubles per block of 256 particles) of up to kNoAllocMaxN particles.  Each
+// GPU the library runs on holds its own copy until the process ends.  In host
+// code this name stands for the device array but is not its address: kernels
+// get the address that hipGetSymbolAddress returned for the current device.
+constexpr long long kNoAllocMaxN = 1LL << 25;
+constexpr int kCgBS = 256;
+static __device__ __align__(256) double scratch[5 * (kNoAllocMaxN / kCgBS)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up once per device.
+mdlg_status scratch_of_current_device(double** out) {
+    int dev = -1;
+    MDLG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(MDLG_EINVAL, "mdlg_coarse_grain_noalloc: device index beyond " + std::to_string(kMaxDevices));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MDLG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MDLG_OK;
+}
+
+mdlg_status check_cg_args(const char* who, const mdlg_lattice* lat, double box_l, int64_t n, const double* pos_prev,
+                          const double* pos_cur, const int64_t* counts) {
+    const std::string w(who);
+    if (!lat || !counts) return fail(MDLG_EINVAL, w + ": lat and counts are required");
+    if (n < 0) return fail(MDLG_EINVAL, w + ": n must be >= 0");
+    if (n > 0 && (!pos_prev || !pos_cur)) return fail(MDLG_EINVAL, w + ": positions are required");
+    if (lat->lx < 1 || lat->lx > 46340) return fail(MDLG_EINVAL, w + ": lx must be in [1, 46340]");
+    if (!(box_l > 0.0) || !std::isfinite(box_l)) return fail(MDLG_EINVAL, w + ": box_l must be > 0");
+    if (!std::isfinite(lat->u[0]) || !std::isfinite(lat->u[1])) return fail(MDLG_EINVAL, w + ": u must be finite");
+    return MDLG_OK;
+}
+
+// The event itself, with the moment partials in `mpart` (5 doubles per block).
+hipError_t coarse_grain_launch(const mdlg_lattice* lat, double box_l, int64_t n, const double* pos_prev,
+                               const int32_t* img_prev, int64_t k_prev, const double* pos_cur,
+                               const int32_t* img_cur, int64_t k_cur, int64_t* counts, double* moments,
+                               int32_t* n_event, int32_t* cell_acc, double* mpart, hipStream_t st) {
     const long long lx = lat->lx;
     const long long field = (long long)MDLG_NQ * lx * lx;
     if (n_event) {
         hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((field + 255) / 256)), dim3(256), 0, st, n_event, field);
-        MDLG_HIP(hipGetLastError());
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    if (n == 0) return MDLG_OK;
-    constexpr int BS = 256;
-    const long long nb = (n + BS - 1) / BS;
+    if (n == 0) return hipSuccess;
+    const long long nb = (n + kCgBS - 1) / kCgBS;
     CgArgs a{};
     a.xp = (const double2*)pos_prev;
     a.ip = (const int2*)img_prev;
@@ -165,15 +203,49 @@ extern "C" mdlg_status mdlg_coarse_grain(const mdlg_lattice* lat, double box_l, 
     a.counts = (unsigned long long*)counts;
     a.n_event = n_event;
     a.cell_acc = cell_acc;
-    MDLG_HIP(hipMallocAsync((void**)&a.mpart, sizeof(double) * 5 * nb, st));
-    hipLaunchKernelGGL(k_coarse_grain<BS>, dim3((unsigned)nb), dim3(BS), 0, st, a);
+    a.mpart = mpart;
+    hipLaunchKernelGGL(k_coarse_grain<kCgBS>, dim3((unsigned)nb), dim3(kCgBS), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && moments) {
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)a.mpart, nb, moments);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)mpart, nb, moments);
         e = hipGetLastError();
     }
-    hipError_t e2 = hipFreeAsync(a.mpart, st);
+    return e;
+}
+
+}  // namespace
+
+extern "C" mdlg_status mdlg_coarse_grain(const mdlg_lattice* lat, double box_l, int64_t n, const double* pos_prev,
+                                         const int32_t* img_prev, int64_t k_prev, const double* pos_cur,
+                                         const int32_t* img_cur, int64_t k_cur, int64_t* counts, double* moments,
+                                         int32_t* n_event, int32_t* cell_acc, void* stream) {
+    mdlg_status s = check_cg_args("mdlg_coarse_grain", lat, box_l, n, pos_prev, pos_cur, counts);
+    if (s != MDLG_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    double* mpart = nullptr;
+    if (n > 0) MDLG_HIP(hipMallocAsync((void**)&mpart, sizeof(double) * 5 * ((n + kCgBS - 1) / kCgBS), st));
+    hipError_t e = coarse_grain_launch(lat, box_l, n, pos_prev, img_prev, k_prev, pos_cur, img_cur, k_cur, counts,
+                                       moments, n_event, cell_acc, mpart, st);
+    hipError_t e2 = mpart ? hipFreeAsync(mpart, st) : hipSuccess;
     MDLG_HIP(e);
     MDLG_HIP(e2);
+    return MDLG_OK;
+}
+
+extern "C" mdlg_status mdlg_coarse_grain_noalloc(const mdlg_lattice* lat, double box_l, int64_t n,
+                                                 const double* pos_prev, const int32_t* img_prev, int64_t k_prev,
+                                                 const double* pos_cur, const int32_t* img_cur, int64_t k_cur,
+                                                 int64_t* counts, double* moments, int32_t* n_event,
+                                                 int32_t* cell_acc, void* stream) {
+    mdlg_status s = check_cg_args("mdlg_coarse_grain_noalloc", lat, box_l, n, pos_prev, pos_cur, counts);
+    if (s != MDLG_OK) return s;
+    if (n > kNoAllocMaxN)
+        return fail(MDLG_EINVAL, "mdlg_coarse_grain_noalloc: n = " + std::to_string(n) + " exceeds the limit of " +
+                                     std::to_string(kNoAllocMaxN) + " particles of its fixed scratch");
+    double* mpart = nullptr;
+    s = scratch_of_current_device(&mpart);
+    if (s != MDLG_OK) return s;
+    MDLG_HIP(coarse_grain_launch(lat, box_l, n, pos_prev, img_prev, k_prev, pos_cur, img_cur, k_cur, counts, moments,
+                                 n_event, cell_acc, mpart, (hipStream_t)stream));
     return MDLG_OK;
 }
