@@ -57,7 +57,7 @@ struct RepDev {
     // fused tiles (two or three steps per launch): pT x pT cells, pts per side, the first global index pt0
     int pt0, pT, pts, pnt;
     // coarse-graining lattice
-    int lx, pad_;
+    int lx, npad;  // lattice cells per side; pad slots after the replica's particles
     double inv_lat, sx, sy;  // lx / L; frame drift per coarse step (u * dx)
     long long cacc0;         // offset of this replica in cell_acc
 };
@@ -76,7 +76,8 @@ struct StepArgs {
     double2* __restrict__ snap;
     unsigned long long* __restrict__ counts;
     double* __restrict__ mpart;
-    int* __restrict__ hpart;
+    int* __restrict__ hpart;                 // [component][pstride]: histogram partials per tile
+    int pstride;                             // tiles per component row of hpart / mpart
     const int* __restrict__ ttile_rep;
     const int* __restrict__ tinfo;
     int nrep;
@@ -91,9 +92,15 @@ struct StepArgs {
     const unsigned short* __restrict__ tlist;   // [tiles][maxnb][kPairCap]: neighbours as staged indices
     const unsigned char* __restrict__ tcnt;     // [tiles][kPairCap]: neighbour counts of all rings but the last
     int maxnb;
+    int rings;                                  // cell rings staged around a fused tile
     const int* __restrict__ ptile_rep;          // [tiles] replica
     int* __restrict__ cell_acc;
     const long long* __restrict__ event_k;
+    // cell binning on the last launch before a rebuild (counting sort input)
+    int* __restrict__ cnt;
+    int* __restrict__ key;
+    int* __restrict__ rank;
+    const double2* __restrict__ pref;
     // observation
     const int* __restrict__ id;
     double2* opos;
@@ -491,13 +498,13 @@ __global__ __launch_bounds__(BS) void k_step_tile(StepArgs a) {
             red[tid >> 6][3] = m3;
         }
         __syncthreads();
-        if (tid < MDLG_NCOUNTS) a.hpart[(long long)t * MDLG_NCOUNTS + tid] = hist[tid];
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tid * a.pstride + t] = hist[tid];
         if (tid < 4) {
             double sum = 0.0;
             for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
-            a.mpart[(long long)t * MDLG_NMOMENTS + 1 + tid] = sum;
+            a.mpart[(long long)(1 + tid) * a.pstride + t] = sum;
         }
-        if (tid == 0) a.mpart[(long long)t * MDLG_NMOMENTS] = 2.0 * (double)nown;
+        if (tid == 0) a.mpart[t] = 2.0 * (double)nown;
     }
 }
 
@@ -656,13 +663,13 @@ __global__ __launch_bounds__(BS) void k_step_gather(StepArgs a) {
             red[tid >> 6][3] = m3;
         }
         __syncthreads();
-        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tile * MDLG_NCOUNTS + tid] = hist[tid];
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tid * a.pstride + tile] = hist[tid];
         if (tid < 4) {
             double sum = 0.0;
             for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
-            a.mpart[(long long)tile * MDLG_NMOMENTS + 1 + tid] = sum;
+            a.mpart[(long long)(1 + tid) * a.pstride + tile] = sum;
         }
-        if (tid == 0) a.mpart[(long long)tile * MDLG_NMOMENTS] = 2.0 * (double)nact_blk;
+        if (tid == 0) a.mpart[tile] = 2.0 * (double)nact_blk;
     }
 }
 
@@ -683,6 +690,14 @@ __device__ __forceinline__ double recip(double x) {
     const double r = __builtin_amdgcn_rcp(x);
     const double e = fma(-x, r, 1.0);
     return fma(fma(e, e, e), r, r);
+}
+
+// Squared separation tested against the neighbour-list range, rounded as
+// written (the same expression wherever lists are built).
+__device__ __forceinline__ bool within_list_range(double dx, double dy, double rl2) {
+#pragma clang fp contract(off)
+    const double r2 = dx * dx + dy * dy;
+    return r2 < rl2;
 }
 
 // Neighbour lists: for every slot, the slots within rc + skin (the cell width)
@@ -731,7 +746,7 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
             const double2 q = pos[k];
             const double dx = min_image_rint(p.x - q.x, R.L, invL);
             const double dy = min_image_rint(p.y - q.y, R.L, invL);
-            if (dx * dx + dy * dy < rl2) {
+            if (within_list_range(dx, dy, rl2)) {
                 int d = k - s;
                 if (2 * d >= R.n) d -= R.n;
                 else if (2 * d < -R.n) d += R.n;
@@ -951,32 +966,33 @@ __global__ __launch_bounds__(BS) void k_step_nlist(StepArgs a) {
             red[tid >> 6][3] = m3;
         }
         __syncthreads();
-        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tile * MDLG_NCOUNTS + tid] = hist[tid];
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tid * a.pstride + tile] = hist[tid];
         if (tid < 4) {
             double sum = 0.0;
             for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
-            a.mpart[(long long)tile * MDLG_NMOMENTS + 1 + tid] = sum;
+            a.mpart[(long long)(1 + tid) * a.pstride + tile] = sum;
         }
-        if (tid == 0) a.mpart[(long long)tile * MDLG_NMOMENTS] = 2.0 * (double)nact_blk;
+        if (tid == 0) a.mpart[tile] = 2.0 * (double)nact_blk;
     }
 }
 
-// Two consecutive ordinary steps per launch.  The box is cut into square tiles
-// of pT x pT cells; a block owns the particles of one tile.  Its staged set is
-// those particles (owned), then the particles of the ring of cells around the
-// tile (ring 1), then those of the next ring (ring 2).  Neighbour lists reach
-// one cell width, so ring 2 holds every neighbour of a ring-1 particle and
-// ring 1 every neighbour of an owned one.  The block loads the staged
-// positions (and the velocities of owned and ring-1 particles) into LDS once;
-// the first step advances owned and ring-1 particles from LDS (ring-1
-// particles are advanced by their own tiles too: the work is repeated, not
-// shared), the second step the owned ones, both through per-tile neighbour
-// lists of staged indices built at the rebuild.  Both steps run the same force
-// and update code as the one-step kernel, in the same neighbour order, so the
-// result equals two one-step launches bit for bit.  Velocities go to a second
-// buffer: other tiles still read the old ones.
+// Fused tiles: several consecutive ordinary steps per launch.  The box is cut
+// into square tiles of pT x pT cells; a block owns the particles of one tile.
+// Its staged set is those particles (owned), then the particles of the ring of
+// cells around the tile (ring 1), then those of the next rings (`rings` in
+// all, two or three).  Neighbour lists reach one cell width, so ring k + 1
+// holds every neighbour of a ring-k particle.  A launch of NS <= rings steps
+// loads the positions of the owned particles and rings 1 .. NS (and the
+// velocities of owned and rings 1 .. NS - 1) into LDS once; step j advances
+// the owned particles and rings 1 .. NS - j from the previous step's positions
+// in LDS (ring particles are advanced by their own tiles too: the halo work is
+// repeated, not shared), through per-tile neighbour lists of staged indices
+// built at the rebuild.  Every step runs the same force and update code as the
+// one-step kernel, in the same neighbour order, so NS steps per launch equal NS
+// one-step launches bit for bit.  Velocities go to a second buffer: other
+// tiles still read the old ones.
 constexpr int kPairCap = 768;      // staged particles of one tile (owned + its rings)
-constexpr int kStep2BS = 512;      // threads of the two- and three-step kernels
+constexpr int kStep2BS = 512;      // threads of the fused step kernels and of the tile builder
 constexpr int kPairAutoT = 16;     // smallest tile side (cells) of the default fused choice
 constexpr int kPairTarget = 520;   // staged particles aimed at when choosing the tile side, two rings
 constexpr int kPairTarget3 = 580;  // the same with three rings
@@ -984,6 +1000,201 @@ constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248
 constexpr int kPairBuildBS = 256;  // threads of the tile list builder
 constexpr int kPairHashBits = 11;  // its slot table: 2048 buckets
 constexpr int kPairHash = 1 << kPairHashBits;
+
+// NS ordinary steps of one tile (FIRST: the stored velocity is a full-step one,
+// only as a launch of one step; CG: the last step ends a coarse step, and the
+// owned particles also evaluate the event of Eq.(n_i): lattice index and
+// destination cell, the block's histogram in LDS with one count per wave for
+// the rest velocity, moment partials of the tile in a fixed order; BIN: the
+// launch is the last before a cell-list rebuild, and the owned particles are
+// also binned for its counting sort at their final positions: cell key, rank
+// within the cell by an atomic count, and the drift check against the
+// positions of the list build, the work of k_bin without its pass over the
+// positions).
+template <int BS, bool F32, int NS, bool FIRST, bool CG, bool BIN>
+__global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
+    static_assert(NS >= 1 && NS <= 3 && (!FIRST || NS == 1), "one to three steps; a first step alone");
+    static_assert(BS <= kPairCap && kPairCap <= 2 * BS, "two staged particles per thread at most");
+    constexpr int NB = NS >= 2 ? kPairCap : 1;
+    __shared__ double2 xa[kPairCap];  // staged positions at time t; after step 2 of three
+    __shared__ double2 xb[NB];        // positions after step 1
+    __shared__ double2 vs[kPairCap];  // velocities of the particles advanced in step 1
+    __shared__ char2 wr[NB];          // image changes of owned particles before the last step
+    __shared__ int hist[CG ? MDLG_NCOUNTS : 1];
+    __shared__ double red[CG ? BS / 64 : 1][4];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    // a thread stages q = tid and tid + BS: their slots, and for the first its
+    // neighbour count and first list rows, all read before the tile's counts
+    // and replica arrive (every tile has kPairCap slot and count entries and
+    // maxnb rows; those past the counts are not used)
+    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
+    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
+    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
+    const unsigned int SL = (unsigned int)kPairCap;
+    const int qf = threadIdx.x;
+    const int s_first = list[qf];
+    const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
+    const int nn_first = tc[qf];
+    int pre[kListPre];
+    list_rows(tl, (unsigned int)qf, SL, pre);
+    const int4 c = a.pcnt[t];
+    const int own = c.x;
+    const int nst = NS == 1 ? c.y : (NS == 2 ? c.z : c.w);   // staged positions: owned and rings 1 .. NS
+    const int nvel = NS == 1 ? c.x : (NS == 2 ? c.y : c.z);  // advanced in step 1
+    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
+    const RepDev& R = a.reps[r];
+    const double L = R.L;
+    const double invL = 1.0 / L;
+    const double2* __restrict__ pin = a.pin;
+    // the four state loads in flight together (slot 0 stands in for unused ones)
+    const bool h0 = qf < nst, h1 = qf + BS < nst;
+    const double2 p0 = pin[h0 ? s_first : 0];
+    const double2 v0 = a.vel[qf < nvel ? s_first : 0];
+    const double2 p1 = pin[h1 ? s_second : 0];
+    const double2 v1 = a.vel[qf + BS < nvel ? s_second : 0];
+    long long ek = 0;
+    if (CG) ek = *a.event_k;
+    double2 q0 = make_double2(0.0, 0.0), q1 = q0;  // positions of the list build (drift check)
+    if (BIN) {
+        q0 = a.pref[qf < c.x ? s_first : 0];
+        q1 = a.pref[qf + BS < c.x ? s_second : 0];
+    }
+    // A tile rings + 1 cells or more from every box edge stages particles of
+    // cells 1 .. nc - 2 only; they move less than a cell between rebuilds, so
+    // none crosses the periodic boundary: separations need no image, positions
+    // no wrap and images no update.
+    const int nc = R.nc, T = R.pT, lt = t - R.pt0;
+    const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
+    const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
+    const int edge = a.rings + 1;
+    const bool interior = c0 >= edge && r0 >= edge && c1 <= nc - edge && r1 <= nc - edge;
+    if (h0) xa[qf] = p0;
+    if (qf < nvel) vs[qf] = v0;
+    if (h1) xa[qf + BS] = p1;
+    if (qf + BS < nvel) vs[qf + BS] = v1;
+    if (CG && qf < MDLG_NCOUNTS) hist[qf] = 0;
+    __syncthreads();
+    // an intermediate step: particles [0, count) from src into dst (LDS); the
+    // image changes of owned particles are kept (set on the first step, added
+    // on the second)
+    auto middle = [&](int count, const double2* src, double2* dst, bool first_step) {
+        for (int q = threadIdx.x; q < count; q += BS) {
+            const bool firstq = q == qf;
+            const double2 p = src[q];
+            double2 v = vs[q];
+            const int nn = firstq ? nn_first : tc[q];
+            auto fetch = [&](int k) { return src[k]; };
+            double fx, fy;
+            nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24,
+                                     R.rc2f, R.eps24f, fx, fy, pre, firstq);
+            int wx, wy;
+            const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                        : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+            dst[q] = pn;
+            vs[q] = v;
+            if (q < own && !interior) {
+                if (first_step) {
+                    wr[q] = make_char2((signed char)wx, (signed char)wy);
+                } else {
+                    const char2 w = wr[q];
+                    wr[q] = make_char2((signed char)(w.x + wx), (signed char)(w.y + wy));
+                }
+            }
+        }
+    };
+    const double2* last = xa;
+    if constexpr (NS == 2) {
+        middle(c.y, xa, xb, true);
+        __syncthreads();
+        last = xb;
+    } else if constexpr (NS == 3) {
+        middle(c.z, xa, xb, true);
+        __syncthreads();
+        middle(c.y, xb, xa, false);  // every read of xa is done
+        __syncthreads();
+    }
+    // the last step: owned particles, to global memory
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    int rest = 0;
+    for (int q = threadIdx.x; q < own; q += BS) {
+        const bool firstq = q == qf;
+        const int s = firstq ? s_first : s_second;
+        const double2 p = last[q];
+        double2 v = vs[q];
+        const int nn = firstq ? nn_first : tc[q];
+        auto fetch = [&](int k) { return last[k]; };
+        double fx, fy;
+        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
+                                 R.eps24f, fx, fy, pre, firstq);
+        int wx, wy;
+        const double2 pn = interior ? vv_update<FIRST, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
+                                    : vv_update<FIRST, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
+        if (NS >= 2 && !interior) {
+            const char2 w1 = wr[q];
+            wx += w1.x;
+            wy += w1.y;
+        }
+        if (wx | wy) {
+            int2 im = a.img[s];
+            im.x += wx;
+            im.y += wy;
+            a.img[s] = im;
+        }
+        if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
+        a.pout[s] = pn;
+        a.vout[s] = v;
+        if (BIN) {
+            const int k = R.cell0 + cell_coord(pn.y, R.inv_w, nc) * nc + cell_coord(pn.x, R.inv_w, nc);
+            const double2 q = firstq ? q0 : q1;
+            const double ex = fabs(min_image(pn.x - q.x, L, R.halfL));
+            const double ey = fabs(min_image(pn.y - q.y, L, R.halfL));
+            if (!(ex * ex + ey * ey <= R.skin_half * R.skin_half)) atomicOr(a.err, ERR_SKIN);
+            a.key[s] = k;
+            a.rank[s] = atomicAdd(&a.cnt[k], 1);
+        }
+        if (CG) {
+            const double2 sp = a.snap[s];
+            long long cell;
+            const int idx = cg_index(R, ek, pn, sp, cell);
+            if (idx < MDLG_NQ && a.cell_acc) atomicAdd(&a.cell_acc[R.cacc0 + (long long)idx * R.lx * R.lx + cell], 1);
+            if (idx == 0) ++rest;
+            else atomicAdd(&hist[idx], 1);
+            const double dx = min_image(pn.x - sp.x, L, R.halfL);
+            const double dy = min_image(pn.y - sp.y, L, R.halfL);
+            const double dx2 = dx * dx, dy2 = dy * dy;
+            m0 += dx2 + dy2;
+            m1 += dx2 * dx2 + dy2 * dy2;
+            m2 += dx;
+            m3 += dy;
+            a.snap[s] = pn;
+        }
+    }
+    if (BIN && t == R.pt0 && threadIdx.x == 0) a.cnt[R.cell0 + nc * nc] = R.npad;
+    if (CG) {
+        // rest velocities: one LDS add per wave; then the tile's partials
+        for (int o = 32; o > 0; o >>= 1) rest += __shfl_xor(rest, o, 64);
+        const int tid = threadIdx.x;
+        if ((tid & 63) == 0 && rest) atomicAdd(&hist[0], rest);
+        m0 = wave_sum(m0);
+        m1 = wave_sum(m1);
+        m2 = wave_sum(m2);
+        m3 = wave_sum(m3);
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = m0;
+            red[tid >> 6][1] = m1;
+            red[tid >> 6][2] = m2;
+            red[tid >> 6][3] = m3;
+        }
+        __syncthreads();
+        if (tid < MDLG_NCOUNTS) a.hpart[(long long)tid * a.pstride + t] = hist[tid];
+        if (tid < 4) {
+            double sum = 0.0;
+            for (int w = 0; w < BS / 64; ++w) sum += red[w][tid];
+            a.mpart[(long long)(1 + tid) * a.pstride + t] = sum;
+        }
+        if (tid == 0) a.mpart[t] = 2.0 * (double)own;
+    }
+}
 
 // Per tile, after the neighbour lists: the staged slots, as contiguous slot
 // ranges of the row-major cell order (owned rows; then ring 1: the rows above
@@ -1104,7 +1315,7 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     __shared__ int lq[kPairCap];   // slot of each staged index
     __shared__ int lq0[kPairCap];  // slots in segment order
     __shared__ unsigned char gq[kPairCap];
-    constexpr int kGroups = 64;  // list-row groups 0 .. maxnb / kListU (maxnb <= 248)
+    constexpr int kGroups = 128;  // list-row groups 0 .. maxnb / kListU (maxnb <= 248)
     __shared__ int gcnt[3][kGroups];
     const int ng = maxnb / kListU + 1;
     for (int h = threadIdx.x; h < kPairHash; h += BS) hkey[h] = 0;
@@ -1184,267 +1395,69 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     }
 }
 
-template <int BS, bool F32>
-__global__ __launch_bounds__(BS, 8) void k_step2_nlist(StepArgs a) {
-    __shared__ double2 x0[kPairCap];  // staged positions at time t
-    __shared__ double2 x1[kPairCap];  // owned and ring-1 positions after the first step
-    __shared__ double2 vs[kPairCap];  // owned and ring-1 velocities
-    __shared__ char2 wr[kPairCap];    // first-step image changes of owned particles
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    // a thread stages q = tid and tid + BS: their slots, and for the first its
-    // neighbour count and first list rows, all read before the tile's counts
-    // and replica arrive (every tile has kPairCap slot and count entries and
-    // maxnb rows; those past the counts are not used)
-    static_assert(BS <= kPairCap && kPairCap <= 2 * BS, "two staged particles per thread at most");
-    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
-    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
-    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
-    const unsigned int SL = (unsigned int)kPairCap;
-    const int qf = threadIdx.x;
-    const int s_first = list[qf];
-    const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
-    const int nn_first = tc[qf];
-    int pre[kListPre];
-    list_rows(tl, (unsigned int)qf, SL, pre);
-    const int4 c = a.pcnt[t];
-    const int own = c.x, mid = c.y, tot = c.z;  // two steps stage the owned particles and rings 1, 2
-    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
-    const RepDev& R = a.reps[r];
-    const double L = R.L;
-    const double invL = 1.0 / L;
-    const double2* __restrict__ pin = a.pin;
-    // the four state loads in flight together (slot 0 stands in for unused ones)
-    const bool h0 = qf < tot, h1 = qf + BS < tot;
-    const double2 p0 = pin[h0 ? s_first : 0];
-    const double2 v0 = a.vel[qf < mid ? s_first : 0];
-    const double2 p1 = pin[h1 ? s_second : 0];
-    const double2 v1 = a.vel[qf + BS < mid ? s_second : 0];
-    // A tile three cells or more from every box edge stages particles of cells
-    // 1 .. nc - 2 only; they move less than a cell between rebuilds, so none
-    // crosses the periodic boundary: separations need no image, positions no
-    // wrap and images no update.
-    const int nc = R.nc, T = R.pT, lt = t - R.pt0;
-    const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
-    const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
-    const bool interior = c0 >= 3 && r0 >= 3 && c1 <= nc - 3 && r1 <= nc - 3;
-    if (h0) x0[qf] = p0;
-    if (qf < mid) vs[qf] = v0;
-    if (h1) x0[qf + BS] = p1;
-    if (qf + BS < mid) vs[qf + BS] = v1;
-    __syncthreads();
-    // first step: owned and ring-1 particles
-    for (int q = threadIdx.x; q < mid; q += BS) {
-        const bool firstq = q == qf;
-        const double2 p = x0[q];
-        double2 v = vs[q];
-        const int nn = firstq ? nn_first : tc[q];
-        auto fetch = [&](int k) { return x0[k]; };
-        double fx, fy;
-        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
-                         fx, fy, pre, firstq);
-        int wx, wy;
-        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
-                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        x1[q] = pn;
-        vs[q] = v;
-        if (q < own && !interior) wr[q] = make_char2((signed char)wx, (signed char)wy);
-    }
-    __syncthreads();
-    // second step: owned particles, the same lists into the first step's positions
-    for (int q = threadIdx.x; q < own; q += BS) {
-        const bool firstq = q == qf;
-        const int s = firstq ? s_first : s_second;
-        const double2 p = x1[q];
-        double2 v = vs[q];
-        const int nn = firstq ? nn_first : tc[q];
-        auto fetch = [&](int k) { return x1[k]; };
-        double fx, fy;
-        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
-                         fx, fy, pre, firstq);
-        int wx, wy;
-        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
-                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        if (!interior) {
-            const char2 w1 = wr[q];
-            wx += w1.x;
-            wy += w1.y;
-        }
-        if (wx | wy) {
-            int2 im = a.img[s];
-            im.x += wx;
-            im.y += wy;
-            a.img[s] = im;
-        }
-        if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
-        a.pout[s] = pn;
-        a.vout[s] = v;
-    }
-}
-
-// Three consecutive ordinary steps per launch, the two-step scheme with one
-// more ring: the block stages the owned particles and three rings; step 1
-// advances owned and rings 1, 2, step 2 owned and ring 1, step 3 the owned
-// particles, each from the previous step's positions in LDS through the same
-// per-tile lists.  Equal to three one-step launches bit for bit.
-template <int BS, bool F32>
-__global__ __launch_bounds__(BS, 8) void k_step3_nlist(StepArgs a) {
-    __shared__ double2 xa[kPairCap];  // staged positions at time t, then owned and ring 1 after step 2
-    __shared__ double2 xb[kPairCap];  // owned, rings 1 and 2 after step 1
-    __shared__ double2 vs[kPairCap];  // velocities of owned, rings 1 and 2
-    __shared__ char2 wr[kPairCap];    // image changes of owned particles in steps 1 and 2
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    // staging as in k_step2_nlist: every load issued before the first wait
-    static_assert(BS <= kPairCap && kPairCap <= 2 * BS, "two staged particles per thread at most");
-    const int* __restrict__ list = a.plist + (long long)t * kPairCap;
-    const unsigned short* __restrict__ tl = a.tlist + (long long)t * a.maxnb * kPairCap;
-    const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
-    const unsigned int SL = (unsigned int)kPairCap;
-    const int qf = threadIdx.x;
-    const int s_first = list[qf];
-    const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
-    const int nn_first = tc[qf];
-    int pre[kListPre];
-    list_rows(tl, (unsigned int)qf, SL, pre);
-    const int4 c = a.pcnt[t];
-    const int own = c.x, n1 = c.y, n2 = c.z, tot = c.w;
-    const int r = a.nrep == 1 ? 0 : __builtin_amdgcn_readfirstlane(a.ptile_rep[t]);
-    const RepDev& R = a.reps[r];
-    const double L = R.L;
-    const double invL = 1.0 / L;
-    const double2* __restrict__ pin = a.pin;
-    const bool h0 = qf < tot, h1 = qf + BS < tot;
-    const double2 p0 = pin[h0 ? s_first : 0];
-    const double2 v0 = a.vel[qf < n2 ? s_first : 0];
-    const double2 p1 = pin[h1 ? s_second : 0];
-    const double2 v1 = a.vel[qf + BS < n2 ? s_second : 0];
-    // staged cells 1 .. nc - 2 only (tiles four cells or more from every edge):
-    // no staged particle crosses the periodic boundary between rebuilds (no
-    // image, no wrap, no image update)
-    const int nc = R.nc, T = R.pT, lt = t - R.pt0;
-    const int c0 = (lt % R.pts) * T, r0 = (lt / R.pts) * T;
-    const int c1 = min(c0 + T, nc), r1 = min(r0 + T, nc);
-    const bool interior = c0 >= 4 && r0 >= 4 && c1 <= nc - 4 && r1 <= nc - 4;
-    if (h0) xa[qf] = p0;
-    if (qf < n2) vs[qf] = v0;
-    if (h1) xa[qf + BS] = p1;
-    if (qf + BS < n2) vs[qf + BS] = v1;
-    __syncthreads();
-    // step 1: owned, rings 1 and 2, from xa into xb
-    for (int q = threadIdx.x; q < n2; q += BS) {
-        const bool firstq = q == qf;
-        const double2 p = xa[q];
-        double2 v = vs[q];
-        const int nn = firstq ? nn_first : tc[q];
-        auto fetch = [&](int k) { return xa[k]; };
-        double fx, fy;
-        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
-                         fx, fy, pre, firstq);
-        int wx, wy;
-        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
-                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        xb[q] = pn;
-        vs[q] = v;
-        if (q < own && !interior) wr[q] = make_char2((signed char)wx, (signed char)wy);
-    }
-    __syncthreads();
-    // step 2: owned and ring 1, from xb into xa (every read of xa is done)
-    for (int q = threadIdx.x; q < n1; q += BS) {
-        const bool firstq = q == qf;
-        const double2 p = xb[q];
-        double2 v = vs[q];
-        const int nn = firstq ? nn_first : tc[q];
-        auto fetch = [&](int k) { return xb[k]; };
-        double fx, fy;
-        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
-                         fx, fy, pre, firstq);
-        int wx, wy;
-        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
-                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        xa[q] = pn;
-        vs[q] = v;
-        if (q < own && !interior) {
-            const char2 w = wr[q];
-            wr[q] = make_char2((signed char)(w.x + wx), (signed char)(w.y + wy));
-        }
-    }
-    __syncthreads();
-    // step 3: owned particles, from xa to global memory
-    for (int q = threadIdx.x; q < own; q += BS) {
-        const bool firstq = q == qf;
-        const int s = firstq ? s_first : s_second;
-        const double2 p = xa[q];
-        double2 v = vs[q];
-        const int nn = firstq ? nn_first : tc[q];
-        auto fetch = [&](int k) { return xa[k]; };
-        double fx, fy;
-        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f, R.eps24f,
-                         fx, fy, pre, firstq);
-        int wx, wy;
-        const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
-                                    : vv_update<false, true>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy);
-        if (!interior) {
-            const char2 w1 = wr[q];
-            wx += w1.x;
-            wy += w1.y;
-        }
-        if (wx | wy) {
-            int2 im = a.img[s];
-            im.x += wx;
-            im.y += wy;
-            a.img[s] = im;
-        }
-        if (!isfinite(pn.x) || !isfinite(pn.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(a.err, ERR_NONFINITE);
-        a.pout[s] = pn;
-        a.vout[s] = v;
-    }
-}
-
 // End of a coarse step: per replica and component, the fixed-order sum over
 // the replica's tiles of the histogram and moment partials is added to the
-// caller's accumulators.  Block (r, c): c < 50 counts, c >= 50 moments.
-// The last block to finish advances the coarse-step index.
+// caller's accumulators.  Block (r, c): c < 50 counts, c >= 50 moments.  Tiles
+// of the step kernel that wrote the partials: mode 0 slot tiles, 1 cell tiles,
+// 2 fused tiles.  Partials are stored component-major, so a block reads one
+// contiguous row; each thread issues its loads (up to kFinishU per chunk of
+// 256 kFinishU tiles) together and sums them in order, then a wave tree and
+// the waves in order finish the block.  Block 0 advances the coarse-step
+// index (no kernel of this launch reads it).
+constexpr int kFinishU = 16;
+
 __global__ __launch_bounds__(256) void k_cg_finish(const int* __restrict__ hpart, const double* __restrict__ mpart,
-                                                   const RepDev* __restrict__ reps, unsigned long long* counts,
-                                                   double* moments, long long* event_k, unsigned int* done,
-                                                   int cell_tiles) {
-    __shared__ double red[256];
-    __shared__ long long redi[256];
+                                                   int pstride, const RepDev* __restrict__ reps,
+                                                   unsigned long long* counts, double* moments, long long* event_k,
+                                                   int mode) {
+    __shared__ double red[4];
+    __shared__ long long redi[4];
     const int r = blockIdx.x / (MDLG_NCOUNTS + MDLG_NMOMENTS);
     const int c = blockIdx.x % (MDLG_NCOUNTS + MDLG_NMOMENTS);
     const RepDev& R = reps[r];
-    const int tid = threadIdx.x;
-    const int b0 = cell_tiles ? R.ttile0 : R.tile0;
-    const int b1 = b0 + (cell_tiles ? R.nttile : R.ntile);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int b0 = mode == 2 ? R.pt0 : (mode == 1 ? R.ttile0 : R.tile0);
+    const int nb = mode == 2 ? R.pnt : (mode == 1 ? R.nttile : R.ntile);
     if (c < MDLG_NCOUNTS) {
+        const int* __restrict__ row = hpart + (long long)c * pstride + b0;
         long long sum = 0;
-        for (int b = b0 + tid; b < b1; b += 256) sum += hpart[(long long)b * MDLG_NCOUNTS + c];
-        redi[tid] = sum;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) redi[tid] += redi[tid + o];
-            __syncthreads();
+        for (int base = 0; base < nb; base += 256 * kFinishU) {
+            int v[kFinishU];
+#pragma unroll
+            for (int u = 0; u < kFinishU; ++u) {
+                const int b = base + tid + u * 256;
+                v[u] = b < nb ? row[b] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kFinishU; ++u) sum += v[u];
         }
-        if (tid == 0 && redi[0]) counts[(long long)r * MDLG_NCOUNTS + c] += (unsigned long long)redi[0];
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == 0) redi[wv] = sum;
+        __syncthreads();
+        if (tid == 0) {
+            const long long tot = redi[0] + redi[1] + redi[2] + redi[3];
+            if (tot) counts[(long long)r * MDLG_NCOUNTS + c] += (unsigned long long)tot;
+        }
     } else {
         const int j = c - MDLG_NCOUNTS;
+        const double* __restrict__ row = mpart + (long long)j * pstride + b0;
         double sum = 0.0;
-        for (int b = b0 + tid; b < b1; b += 256) sum += mpart[(long long)b * MDLG_NMOMENTS + j];
-        red[tid] = sum;
+        for (int base = 0; base < nb; base += 256 * kFinishU) {
+            double v[kFinishU];
+#pragma unroll
+            for (int u = 0; u < kFinishU; ++u) {
+                const int b = base + tid + u * 256;
+                v[u] = b < nb ? row[b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kFinishU; ++u) sum += v[u];
+        }
+        sum = wave_sum(sum);
+        if (lane == 0) red[wv] = sum;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) red[tid] += red[tid + o];
-            __syncthreads();
-        }
-        if (tid == 0) moments[(long long)r * MDLG_NMOMENTS + j] += red[0];
+        if (tid == 0) moments[(long long)r * MDLG_NMOMENTS + j] += ((red[0] + red[1]) + red[2]) + red[3];
     }
-    if (tid == 0) {
-        __threadfence();
-        const unsigned int prev = atomicAdd(done, 1u);
-        if (prev == gridDim.x - 1) {
-            *event_k += 1;
-            *done = 0u;
-        }
-    }
+    if (blockIdx.x == 0 && tid == 0) *event_k += 1;
 }
 
 // Observation at the current positions: forces, full-step velocities, state
@@ -1714,7 +1727,7 @@ __global__ void k_place(const int* __restrict__ cs, const int* __restrict__ key,
     b.img_n[dst] = b.img_o[src];
     b.id_n[dst] = myid;
     b.snap_n[dst] = b.snap_o[src];
-    cellof[dst] = c;
+    if (cellof) cellof[dst] = c;  // the drift check of the cell-stencil kernels (lists keep positions instead)
 }
 
 // Initial placement: slot slot0_r + j of replica r holds particle off_r + j.
@@ -1779,9 +1792,9 @@ struct RepHost {
 };
 
 struct GraphKey {
-    int K, phase, ppar, opar, vpar;
+    int K, phase, ppar, opar, vpar, binned;
     bool operator<(const GraphKey& o) const {
-        return std::tie(K, phase, ppar, opar, vpar) < std::tie(o.K, o.phase, o.ppar, o.opar, o.vpar);
+        return std::tie(K, phase, ppar, opar, vpar, binned) < std::tie(o.K, o.phase, o.ppar, o.opar, o.vpar, o.binned);
     }
 };
 
@@ -1789,6 +1802,7 @@ struct GraphVal {
     hipGraphExec_t exec;
     int ppar_after, opar_after, vpar_after;
     int events;
+    bool binned_after;
 };
 
 template <typename T>
@@ -1832,7 +1846,7 @@ struct lj_md {
     double2* pref = nullptr;  // positions at the list build
     int maxnb = 0;
     int* d_hpart = nullptr;
-    unsigned int* d_done = nullptr;
+    int pstride = 0;  // tiles per component row of the partials (the most of any kind of tile)
     double2* pos[2] = {nullptr, nullptr};
     double2* vel[2] = {nullptr, nullptr};
     int2* img[2] = {nullptr, nullptr};
@@ -1844,6 +1858,7 @@ struct lj_md {
     int ppar = 0, opar = 0, vpar = 0;  // current buffer of pos / of img, id, snap / of vel
     bool vel_full = true;
     bool have_cellof = false;
+    bool binned = false;  // key, rank and cnt hold the current positions' binning (done by the last step launch)
     bool broken = false;
     int K = 50;
     bool K_auto = true;
@@ -1871,8 +1886,9 @@ struct lj_md {
         std::array<hipGraphExec_t, 3> g;
         int M, tail_events;
         int ppar_after, opar_after, vpar_after;
+        bool binned_after;
     };
-    std::map<std::tuple<int, int, int, int, int>, TimedGraphs> tgraphs;
+    std::map<std::tuple<int, int, int, int, int, int>, TimedGraphs> tgraphs;
     bool use_graphs = true;
 };
 
@@ -1922,6 +1938,7 @@ StepArgs make_args(lj_md* md) {
     a.counts = md->counts;
     a.mpart = md->d_mpart;
     a.hpart = md->d_hpart;
+    a.pstride = md->pstride;
     a.ttile_rep = md->d_ttile_rep;
     a.tinfo = md->d_tinfo;
     a.nrep = md->R;
@@ -1934,10 +1951,15 @@ StepArgs make_args(lj_md* md) {
     a.tlist = md->tlist;
     a.tcnt = md->tcnt;
     a.maxnb = md->maxnb;
+    a.rings = md->rings;
     a.ptile_rep = md->d_ptrep;
     a.cell_acc = md->cell_acc;
     a.event_k = md->d_event_k;
     a.id = md->id[md->opar];
+    a.cnt = md->cnt;
+    a.key = md->key;
+    a.rank = md->rank;
+    a.pref = md->pref;
     return a;
 }
 
@@ -1989,56 +2011,55 @@ hipError_t launch_step(lj_md* md, hipStream_t st, bool first, bool cg, hipEvent_
     if (e != hipSuccess) return e;
     if (cg) {
         hipLaunchKernelGGL(k_cg_finish, dim3(md->R * (MDLG_NCOUNTS + MDLG_NMOMENTS)), dim3(256), 0, st,
-                           (const int*)md->d_hpart, (const double*)md->d_mpart, (const RepDev*)md->d_reps,
-                           md->counts, md->moments, md->d_event_k, md->d_done, md->variant == 2 ? 1 : 0);
+                           (const int*)md->d_hpart, (const double*)md->d_mpart, md->pstride, (const RepDev*)md->d_reps,
+                           md->counts, md->moments, md->d_event_k, md->variant == 2 ? 1 : 0);
         e = hipGetLastError();
     }
     md->ppar ^= 1;
     return e;
 }
 
-// Two ordinary steps in one launch (see k_step2_nlist).
-hipError_t launch_step2(lj_md* md, hipStream_t st) {
-    StepArgs a = make_args(md);
-    const int grid = md->npt;
-    if (md->f32)
-        hipLaunchKernelGGL((k_step2_nlist<kStep2BS, true>), dim3(grid), dim3(kStep2BS), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_step2_nlist<kStep2BS, false>), dim3(grid), dim3(kStep2BS), 0, st, a);
-    md->ppar ^= 1;
-    md->vpar ^= 1;
-    return hipGetLastError();
+template <bool F32, int NS, bool FIRST, bool CG, bool BIN>
+void launch_fused_t(hipStream_t st, int grid, const StepArgs& a) {
+    hipLaunchKernelGGL((k_step_fused<kStep2BS, F32, NS, FIRST, CG, BIN>), dim3(grid), dim3(kStep2BS), 0, st, a);
 }
 
-// Three ordinary steps in one launch (see k_step3_nlist).
-hipError_t launch_step3(lj_md* md, hipStream_t st) {
-    StepArgs a = make_args(md);
-    const int grid = md->npt;
-    if (md->f32)
-        hipLaunchKernelGGL((k_step3_nlist<kStep2BS, true>), dim3(grid), dim3(kStep2BS), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_step3_nlist<kStep2BS, false>), dim3(grid), dim3(kStep2BS), 0, st, a);
-    md->ppar ^= 1;
-    md->vpar ^= 1;
-    return hipGetLastError();
-}
-
-// Ordinary steps that the next launch can take together: up to three (with
-// three-step tiles) or two, fewer when `avail` steps remain or a
-// coarse-graining event falls on one of them; a run of 3k + 1 ordinary steps
-// (k >= 1) starts with a two-step launch, so that it ends without a one-step
-// launch.
-int fuse_len(const lj_md* md, int avail, bool check_events);
-
-// `count` ordinary steps (no coarse-graining event), two per launch where the
-// handle allows it.
-hipError_t launch_plain_steps(lj_md* md, hipStream_t st, int count) {
-    hipError_t e = hipSuccess;
-    while (count > 0 && e == hipSuccess) {
-        const int n = fuse_len(md, count, false);
-        e = n == 3 ? launch_step3(md, st) : (n == 2 ? launch_step2(md, st) : launch_step(md, st, false, false));
-        count -= n;
+template <bool F32, int NS, bool FIRST>
+void launch_fused_cb(hipStream_t st, int grid, const StepArgs& a, bool cg, bool bin) {
+    if (cg) {
+        if (bin) launch_fused_t<F32, NS, FIRST, true, true>(st, grid, a);
+        else launch_fused_t<F32, NS, FIRST, true, false>(st, grid, a);
+    } else {
+        if (bin) launch_fused_t<F32, NS, FIRST, false, true>(st, grid, a);
+        else launch_fused_t<F32, NS, FIRST, false, false>(st, grid, a);
     }
+}
+
+template <bool F32>
+void launch_fused_f(hipStream_t st, int grid, const StepArgs& a, int ns, bool first, bool cg, bool bin) {
+    if (ns == 3) launch_fused_cb<F32, 3, false>(st, grid, a, cg, bin);
+    else if (ns == 2) launch_fused_cb<F32, 2, false>(st, grid, a, cg, bin);
+    else if (first) launch_fused_cb<F32, 1, true>(st, grid, a, cg, bin);
+    else launch_fused_cb<F32, 1, false>(st, grid, a, cg, bin);
+}
+
+// `ns` ordinary steps (ns <= rings) in one launch on the fused tiles (see
+// k_step_fused), the last one with the coarse-graining event and its
+// reduction when `cg`, binning the particles for the next rebuild when `bin`.
+hipError_t launch_fused(lj_md* md, hipStream_t st, int ns, bool first, bool cg, bool bin) {
+    StepArgs a = make_args(md);
+    if (md->f32) launch_fused_f<true>(st, md->npt, a, ns, first, cg, bin);
+    else launch_fused_f<false>(st, md->npt, a, ns, first, cg, bin);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (cg) {
+        hipLaunchKernelGGL(k_cg_finish, dim3(md->R * (MDLG_NCOUNTS + MDLG_NMOMENTS)), dim3(256), 0, st,
+                           (const int*)md->d_hpart, (const double*)md->d_mpart, md->pstride, (const RepDev*)md->d_reps,
+                           md->counts, md->moments, md->d_event_k, 2);
+        e = hipGetLastError();
+    }
+    md->ppar ^= 1;
+    md->vpar ^= 1;
     return e;
 }
 
@@ -2069,11 +2090,14 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     const int o = md->opar;
     const int grid = md->ntile;
     const int check = md->have_cellof ? 1 : 0;
-    switch (md->BS) {
-        case 64: hipLaunchKernelGGL(k_bin<64>, dim3(grid), dim3(64), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
-        case 128: hipLaunchKernelGGL(k_bin<128>, dim3(grid), dim3(128), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
-        case 256: hipLaunchKernelGGL(k_bin<256>, dim3(grid), dim3(256), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
-        default: hipLaunchKernelGGL(k_bin<512>, dim3(grid), dim3(512), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+    // the binning of the counting sort, unless the last step launch did it
+    if (!md->binned) {
+        switch (md->BS) {
+            case 64: hipLaunchKernelGGL(k_bin<64>, dim3(grid), dim3(64), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+            case 128: hipLaunchKernelGGL(k_bin<128>, dim3(grid), dim3(128), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+            case 256: hipLaunchKernelGGL(k_bin<256>, dim3(grid), dim3(256), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+            default: hipLaunchKernelGGL(k_bin<512>, dim3(grid), dim3(512), 0, st, (const double2*)md->pos[md->ppar], (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->cnt, md->key, md->rank, (const int*)md->cellof, check, md->d_err, (const double2*)(md->variant == 3 ? md->pref : nullptr)); break;
+        }
     }
     const int nb = (C + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C, md->bsum);
@@ -2098,7 +2122,7 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     b.snap_o = md->snap[o];
     b.snap_n = md->snap[o ^ 1];
     hipLaunchKernelGGL(k_place, dim3((S + 255) / 256), dim3(256), 0, st, (const int*)md->cs, (const int*)md->key,
-                       (const int*)md->perm, (const int*)md->permid, S, b, md->cellof);
+                       (const int*)md->perm, (const int*)md->permid, S, b, md->variant == 3 ? nullptr : md->cellof);
     if (md->variant == 3)
         hipLaunchKernelGGL(k_nlist_build, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
                            (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
@@ -2112,39 +2136,104 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     md->opar ^= 1;
     md->vpar ^= 1;
     md->have_cellof = true;
+    md->binned = false;
     md->since_rebuild = 0;
     return hipGetLastError();
 }
 
-bool event_due(lj_md* md, long long t_after) { return md->cg_on && (t_after % md->s_cg) == 0; }
+// One launch of a planned run: n steps, the last one ending a coarse step
+// (cg), the first step after initialisation (first: its velocity is a
+// full-step one).
+struct LaunchPlan {
+    int n;
+    bool cg, first;
+};
 
-int fuse_len(const lj_md* md, int avail, bool check_events) {
+// The next launch for `avail` steps without a rebuild, from coarse step
+// counter cg_t: a first step goes alone; otherwise the steps up to the next
+// coarse-graining event (or all of them) are split into launches of up to mx
+// steps with the event on the last step of the last one, which takes mx steps
+// where the split allows it (m = mx k, or a shorter launch or two before it).
+LaunchPlan plan_next(const lj_md* md, long long cg_t, bool vel_full, int avail) {
     const int mx = md->three_step ? 3 : (md->two_step ? 2 : 1);
-    // m: ordinary steps before the next event (or the end of the run of steps)
+    auto ev_at = [&](int k) { return md->cg_on && (cg_t + k) % md->s_cg == 0; };
+    if (vel_full || mx == 1) return {1, ev_at(1), vel_full};
     int m = 1;
-    while (m < avail && !(check_events && event_due(const_cast<lj_md*>(md), md->cg_t + m + 1))) ++m;
-    if (mx == 3 && m % 3 == 1 && m >= 4) return 2;  // 2 + 2 + 3k: two two-step launches cost less than 3 + 1
-    return std::min(mx, m);
+    while (m < avail && !ev_at(m)) ++m;
+    int n;
+    if (mx == 2) n = (m % 2 == 1) ? 1 : 2;
+    else if (m % 3 == 0) n = 3;
+    else if (m % 3 == 2) n = m >= 8 ? 3 : 2;
+    else n = m == 1 ? 1 : (m >= 10 ? 3 : 2);
+    return {n, ev_at(m) && n == m, false};
 }
 
-// One MD step launched eagerly (rebuild first if due).
-hipError_t eager_step(lj_md* md, hipStream_t st) {
-    hipError_t e;
-    if (md->since_rebuild >= md->K) {
-        e = launch_rebuild(md, st);
-        if (e != hipSuccess) return e;
+// The launches of `count` steps without a rebuild from the current state.
+std::vector<LaunchPlan> plan_steps(const lj_md* md, int count) {
+    std::vector<LaunchPlan> out;
+    long long cg_t = md->cg_t;
+    bool vel_full = md->vel_full;
+    while (count > 0) {
+        const LaunchPlan p = plan_next(md, cg_t, vel_full, count);
+        out.push_back(p);
+        if (md->cg_on) cg_t += p.n;
+        vel_full = false;
+        count -= p.n;
     }
-    const bool ev = event_due(md, md->cg_t + 1);
-    e = launch_step(md, st, md->vel_full, ev);
+    return out;
+}
+
+// Enqueue one planned launch and advance the host counters.
+hipError_t issue(lj_md* md, hipStream_t st, const LaunchPlan& p) {
+    // the launch that completes the cell-list interval bins for the rebuild
+    const bool bin = md->two_step && md->since_rebuild + p.n == md->K;
+    hipError_t e = md->two_step ? launch_fused(md, st, p.n, p.first, p.cg, bin) : launch_step(md, st, p.first, p.cg);
     if (e != hipSuccess) return e;
+    md->binned = bin;
     md->vel_full = false;
-    md->steps_done += 1;
-    md->since_rebuild += 1;
+    md->steps_done += p.n;
+    md->since_rebuild += p.n;
     if (md->cg_on) {
-        md->cg_t += 1;
-        if (ev) md->events += 1;
+        md->cg_t += p.n;
+        if (p.cg) md->events += 1;
     }
     return hipSuccess;
+}
+
+// `count` MD steps from the current state: a rebuild whenever the cell lists
+// are K steps old, planned launches in between.
+hipError_t run_steps(lj_md* md, hipStream_t st, long long count) {
+    hipError_t e = hipSuccess;
+    while (count > 0 && e == hipSuccess) {
+        if (md->since_rebuild >= md->K) {
+            e = launch_rebuild(md, st);
+            if (e != hipSuccess) break;
+        }
+        const int avail = (int)std::min<long long>(count, md->K - md->since_rebuild);
+        const LaunchPlan p = plan_next(md, md->cg_t, md->vel_full, avail);
+        e = issue(md, st, p);
+        count -= p.n;
+    }
+    return e;
+}
+
+// Steps until whole cell-list intervals (rebuild + K steps) hold their
+// coarse-graining events at fixed offsets that end launches: with K a multiple
+// of s_cg the coarse step counter is brought to a fixed residue modulo s_cg,
+// with s_cg a multiple of K modulo K; otherwise events fall at varying offsets
+// of the intervals and no alignment helps (0).  On fused tiles the residue is
+// 2, so that an interval's last event ends the launch before its last one (a
+// launch of two steps): the event and the binning for the rebuild (which the
+// last launch does) then never share a launch, whose registers would not hold
+// both.
+int steps_to_alignment(const lj_md* md) {
+    if (!md->cg_on) return 0;
+    int period = 1;
+    if (md->s_cg <= md->K) period = md->K % md->s_cg == 0 ? md->s_cg : 1;
+    else period = md->s_cg % md->K == 0 ? md->K : 1;
+    const long long residue = (md->two_step && period >= 3) ? 2 : 0;
+    const long long r = ((md->cg_t - residue) % period + period) % period;
+    return r == 0 ? 0 : (int)(period - r);
 }
 
 // What distinguishes the kernel sequence of a unit (rebuild + K steps) starting
@@ -2161,24 +2250,13 @@ int unit_phase(const lj_md* md) {
 
 // rebuild + K steps, replayed from a captured graph.
 mdlg_status graph_unit(lj_md* md, hipStream_t st) {
-    GraphKey key{md->K, unit_phase(md), md->ppar, md->opar, md->vpar};
+    GraphKey key{md->K, unit_phase(md), md->ppar, md->opar, md->vpar, md->binned ? 1 : 0};
     auto it = md->graphs.find(key);
     if (it == md->graphs.end()) {
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
         MDLG_HIP(hipStreamBeginCapture(md->cap, hipStreamCaptureModeThreadLocal));
         hipError_t e = launch_rebuild(md, md->cap);
-        for (int j = 0; j < md->K && e == hipSuccess;) {
-            const bool ev = event_due(md, md->cg_t + 1);
-            const int n = ev ? 1 : fuse_len(md, md->K - j, true);
-            e = n == 3 ? launch_step3(md, md->cap)
-                       : (n == 2 ? launch_step2(md, md->cap) : launch_step(md, md->cap, false, ev));
-            md->since_rebuild += n;
-            if (md->cg_on) {
-                md->cg_t += n;
-                if (ev) md->events += 1;
-            }
-            j += n;
-        }
+        if (e == hipSuccess) e = run_steps(md, md->cap, md->K);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(md->cap, &g);
         if (e != hipSuccess) return fail(MDLG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -2186,12 +2264,13 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
         hipGraphExec_t ex = nullptr;
         MDLG_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
-        GraphVal val{ex, md->ppar, md->opar, md->vpar, (int)(md->events - ev0)};
+        GraphVal val{ex, md->ppar, md->opar, md->vpar, (int)(md->events - ev0), md->binned};
         md->graphs[key] = val;
         // the capture only recorded work: restore the counters, then replay
         md->ppar = key.ppar;
         md->opar = key.opar;
         md->vpar = key.vpar;
+        md->binned = key.binned != 0;
         md->steps_done = steps0;
         md->cg_t = cg_t0;
         md->events = ev0;
@@ -2201,6 +2280,7 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
     md->ppar = it->second.ppar_after;
     md->opar = it->second.opar_after;
     md->vpar = it->second.vpar_after;
+    md->binned = it->second.binned_after;
     md->steps_done += md->K;
     md->since_rebuild = md->K;
     md->have_cellof = true;
@@ -2209,6 +2289,17 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
         md->events += it->second.events;
     }
     return MDLG_OK;
+}
+
+// The length of the next run of steps launched directly (not from a graph):
+// a first step alone, the steps up to the alignment of the intervals, or all
+// that remain when fewer than a whole interval do.  0: a graph unit is next.
+long long eager_len(const lj_md* md, long long nsteps) {
+    if (md->vel_full) return 1;
+    const int align = steps_to_alignment(md);
+    if (align > 0) return std::min<long long>(align, nsteps);
+    if (md->use_graphs && nsteps >= md->K) return 0;
+    return nsteps;
 }
 
 mdlg_status check_params(const lj_params& p, int r) {
@@ -2332,6 +2423,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
             ttiles += d.nttile;
         }
         d.lx = 0;
+        d.npad = h.nslots - (int)q.n;
         h.poff = poff;
         cells += (long long)nc * nc + 1;
         slots += h.nslots;
@@ -2392,9 +2484,11 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     }
 
     auto A = [&](hipError_t e) { return e == hipSuccess; };
+    md->pstride = std::max(std::max(md->TT, md->ntile), md->npt);  // partials of every kind of tile
+    const size_t part_tiles = (size_t)md->pstride;
     bool ok = A(dalloc(&md->d_reps, n_rep)) && A(dalloc(&md->d_tile_rep, md->ntile)) &&
-              A(dalloc(&md->d_ttile_rep, md->TT)) && A(dalloc(&md->d_hpart, (size_t)std::max(md->TT, md->ntile) * MDLG_NCOUNTS)) &&
-              A(dalloc(&md->d_done, 1)) && A(dalloc(&md->d_tinfo, (size_t)md->TT * kTileInfo));
+              A(dalloc(&md->d_ttile_rep, md->TT)) && A(dalloc(&md->d_hpart, part_tiles * MDLG_NCOUNTS)) &&
+              A(dalloc(&md->d_tinfo, (size_t)md->TT * kTileInfo));
     for (int b = 0; b < 2 && ok; ++b)
         ok = A(dalloc(&md->pos[b], md->S)) && A(dalloc(&md->vel[b], md->S)) && A(dalloc(&md->img[b], md->S)) &&
              A(dalloc(&md->id[b], md->S)) && A(dalloc(&md->snap[b], md->S));
@@ -2402,7 +2496,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
          A(dalloc(&md->cellof, md->S)) && A(dalloc(&md->cnt, md->C)) && A(dalloc(&md->cs, (size_t)md->C + 1)) &&
          A(dalloc(&md->bsum, md->nscan)) && A(dalloc(&md->d_err, 1)) && A(dalloc(&md->d_epart, (size_t)md->ntile * 4)) &&
          A(dalloc(&md->d_eout, (size_t)n_rep * 4)) && A(dalloc(&md->d_vmax, 1)) &&
-         A(dalloc(&md->d_mpart, (size_t)std::max(md->TT, md->ntile) * MDLG_NMOMENTS)) && A(dalloc(&md->d_event_k, 1)) &&
+         A(dalloc(&md->d_mpart, part_tiles * MDLG_NMOMENTS)) && A(dalloc(&md->d_event_k, 1)) &&
          A(hipStreamCreateWithFlags(&md->cap, hipStreamNonBlocking));
     if (ok && md->variant == 3) {
         // list capacity: twice the mean neighbour count of the densest replica plus 16
@@ -2453,7 +2547,6 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
     if (e == hipSuccess) e = hipMemcpy(md->d_ttile_rep, ttrep.data(), sizeof(int) * md->TT, hipMemcpyHostToDevice);
     if (e == hipSuccess && md->two_step)
         e = hipMemcpy(md->d_ptrep, ptrep.data(), sizeof(int) * md->npt, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemsetAsync(md->d_done, 0, sizeof(unsigned int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_err, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(md->cnt, 0, sizeof(int) * md->C, st);
     if (e == hipSuccess) e = hipMemsetAsync(md->d_vmax, 0, sizeof(unsigned long long), st);
@@ -2572,15 +2665,16 @@ extern "C" mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream) {
     if (nsteps < 0) return fail(MDLG_EINVAL, "lj_md_step: nsteps must be >= 0");
     hipStream_t st = (hipStream_t)stream;
     while (nsteps > 0) {
-        if (!md->vel_full && md->use_graphs && nsteps >= md->K) {
+        const long long n = eager_len(md, nsteps);
+        if (n == 0) {
             mdlg_status s = graph_unit(md, st);
             if (s != MDLG_OK) return s;
             nsteps -= md->K;
             continue;
         }
-        hipError_t e = eager_step(md, st);
+        hipError_t e = run_steps(md, st, n);
         if (e != hipSuccess) return fail(MDLG_EHIP, std::string("lj_md_step: ") + hipGetErrorString(e));
-        nsteps -= 1;
+        nsteps -= n;
     }
     return MDLG_OK;
 }
@@ -2610,11 +2704,14 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     if (md->broken) return fail(MDLG_EINVAL, "lj_md_step_timed: handle is unusable after a device fault");
     if (nunits < 3 || nunits > 10000) return fail(MDLG_EINVAL, "lj_md_step_timed: nunits must be in [3, 1e4]");
     hipStream_t st = (hipStream_t)stream;
-    if (md->vel_full) {
-        hipError_t e = eager_step(md, st);
+    // direct launches up to the first interval aligned with the coarse steps
+    while (md->vel_full || steps_to_alignment(md) > 0) {
+        const long long n = md->vel_full ? 1 : steps_to_alignment(md);
+        hipError_t e = run_steps(md, st, n);
         if (e != hipSuccess) return fail(MDLG_EHIP, std::string("lj_md_step_timed: ") + hipGetErrorString(e));
     }
     const int K = md->K;
+    const int mx = md->three_step ? 3 : (md->two_step ? 2 : 1);
     struct UnitRec {
         std::array<int, 4> ev;
         int M, tail_events;
@@ -2627,44 +2724,37 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     mdlg_status status = MDLG_OK;
     for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
         const int phase = unit_phase(md);
-        const auto key = std::make_tuple(K, md->ppar, md->opar, md->vpar, phase);
+        const auto key = std::make_tuple(K, md->ppar, md->opar, md->vpar, phase, md->binned ? 1 : 0);
         auto it = cache.find(key);
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
-        Graphs G{{nullptr, nullptr, nullptr}, K, 0, 0, 0, 0};
+        Graphs G{{nullptr, nullptr, nullptr}, 0, 0, 0, 0, 0, false};
         if (it == cache.end()) {
-            // ordinary steps at the start of the unit, before its first coarse-graining step
-            if (md->cg_on) {
-                const long long to_event = md->s_cg - (md->cg_t % md->s_cg);
-                if (to_event <= K) G.M = (int)to_event - 1;
+            // the unit's launches: the leading full-length ones without an
+            // event, then the rest (shorter launches and the events)
+            const std::vector<LaunchPlan> plan = plan_steps(md, K);
+            size_t lead = 0;
+            while (lead < plan.size() && plan[lead].n == mx && !plan[lead].cg) {
+                G.M += plan[lead].n;
+                ++lead;
             }
-            const int M = G.M;
             status = capture(md, [&](hipStream_t cs) { return launch_rebuild(md, cs); }, &G.g[0]);
-            if (status == MDLG_OK)
-                status = capture(md, [&](hipStream_t cs) {
-                    hipError_t e = launch_plain_steps(md, cs, M);
-                    md->cg_t += md->cg_on ? M : 0;
-                    return e;
-                }, &G.g[1]);
-            if (status == MDLG_OK)
+            if (status == MDLG_OK && lead > 0)
                 status = capture(md, [&](hipStream_t cs) {
                     hipError_t e = hipSuccess;
-                    for (int j = M; j < K && e == hipSuccess;) {
-                        const bool ev = event_due(md, md->cg_t + 1);
-                        const int n = ev ? 1 : fuse_len(md, K - j, true);
-                        e = n == 3 ? launch_step3(md, cs)
-                                   : (n == 2 ? launch_step2(md, cs) : launch_step(md, cs, false, ev));
-                        if (md->cg_on) {
-                            md->cg_t += n;
-                            if (ev) md->events += 1;
-                        }
-                        j += n;
-                    }
+                    for (size_t i = 0; i < lead && e == hipSuccess; ++i) e = issue(md, cs, plan[i]);
+                    return e;
+                }, &G.g[1]);
+            if (status == MDLG_OK && lead < plan.size())
+                status = capture(md, [&](hipStream_t cs) {
+                    hipError_t e = hipSuccess;
+                    for (size_t i = lead; i < plan.size() && e == hipSuccess; ++i) e = issue(md, cs, plan[i]);
                     return e;
                 }, &G.g[2]);
             G.tail_events = (int)(md->events - ev0);
             G.ppar_after = md->ppar;
             G.opar_after = md->opar;
             G.vpar_after = md->vpar;
+            G.binned_after = md->binned;
             if (status != MDLG_OK) {
                 for (auto x : G.g)
                     if (x) (void)hipGraphExecDestroy(x);
@@ -2676,6 +2766,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
             md->ppar = std::get<1>(key);
             md->opar = std::get<2>(key);
             md->vpar = std::get<3>(key);
+            md->binned = std::get<5>(key) != 0;
             md->steps_done = steps0;
             md->cg_t = cg_t0;
             md->events = ev0;
@@ -2707,6 +2798,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
         md->ppar = G.ppar_after;
         md->opar = G.opar_after;
         md->vpar = G.vpar_after;
+        md->binned = G.binned_after;
         md->steps_done += K;
         md->since_rebuild = K;
         md->have_cellof = true;
@@ -2720,10 +2812,8 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     if (status == MDLG_OK) {
         // units up to the last capture of this call ran while the host captured
         // graphs (the GPU idled meanwhile): they warm up and are not counted.
-        // The later units' times are summed, and each total divided by the
-        // number of kernels (or graphs) behind it: averages per launch.
-        double sum_plain = 0.0, sum_event = 0.0, sum_rebuild = 0.0;
-        long long n_plain = 0, n_events = 0, n_rebuild = 0, n_tail_plain = 0;
+        double sum_lead = 0.0, sum_rest = 0.0, sum_rebuild = 0.0;
+        long long n_lead = 0, n_events = 0, n_rebuild = 0;
         size_t first = last_capture >= 0 ? (size_t)last_capture + 1 : 0;
         if (first >= order.size()) first = order.size() - 1;
         for (size_t ui = first; ui < order.size(); ++ui) {
@@ -2732,24 +2822,18 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
             for (int q = 0; q < 3; ++q) (void)hipEventElapsedTime(&t[q], evs[rec.ev[q]], evs[rec.ev[q + 1]]);
             sum_rebuild += t[0];
             n_rebuild += 1;
-            sum_plain += t[1];
-            n_plain += rec.M;
+            sum_lead += t[1];
+            n_lead += rec.M;
             if (rec.tail_events > 0) {
-                sum_event += t[2];
+                sum_rest += t[2];
                 n_events += rec.tail_events;
-                n_tail_plain += K - rec.M - rec.tail_events;
-            } else {
-                sum_plain += t[2];
-                n_plain += K - rec.M;
             }
         }
-        const double plain = n_plain ? sum_plain / (double)n_plain : 0.0;
-        // the tails' ordinary steps are priced at the average ordinary step
-        ms_out[0] = plain;
-        ms_out[1] = n_events ? (sum_event - (double)n_tail_plain * plain) / (double)n_events : 0.0;
+        ms_out[0] = n_lead ? sum_lead / (double)n_lead : 0.0;
+        ms_out[1] = n_events ? sum_rest / (double)n_events : 0.0;
         ms_out[2] = n_rebuild ? sum_rebuild / (double)n_rebuild : 0.0;
         if (n_out) {
-            n_out[0] = (int32_t)n_plain;
+            n_out[0] = (int32_t)n_lead;
             n_out[1] = (int32_t)n_events;
             n_out[2] = (int32_t)n_rebuild;
         }
@@ -2925,7 +3009,7 @@ extern "C" void lj_md_destroy(lj_md* md) {
     if (!md) return;
     clear_graphs(md);
     if (md->cap) (void)hipStreamDestroy(md->cap);
-    void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->d_done, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
+    void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
                     md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm, md->permid,
                     md->cellof, md->cnt, md->cs, md->bsum, md->d_err, md->d_epart, md->d_eout, md->d_vmax,
                     md->d_mpart, md->d_event_k, md->d_ptrep, md->plist, md->pcnt, md->tlist, md->tcnt};
