@@ -67,9 +67,13 @@ def parse():
     ap.add_argument("--train-batch", type=int, default=4096, help="surrogate: minibatch")
     ap.add_argument("--groups", type=int, default=4, help="surrogate: replica groups (80 replicas each)")
     ap.add_argument("--paper-replicas", type=int, default=4, help="paper: independent systems of 99,856 particles")
-    ap.add_argument("--events", type=int, default=20, help="paper: coarse-graining events per Table 1 row")
+    ap.add_argument("--events", type=int, default=20, help="paper: coarse-graining events per Table 1 row (2000 in the paper)")
     ap.add_argument("--equil", type=int, default=1000000, help="paper: MD steps discarded before the sweep")
     ap.add_argument("--rows", default="", help="paper: comma-separated Table 1 rows (0-11); default all")
+    ap.add_argument("--stop-at", type=int, default=0, help="paper: stop the sweep before this MD step (0: run to the end)")
+    ap.add_argument("--checkpoint", default="", help="paper: write state and accumulators here when stopping early")
+    ap.add_argument("--resume", default="", help="paper: continue the sweep from a checkpoint")
+    ap.add_argument("--crosscheck", type=int, default=1, help="paper: one coarse step of row 0 by the oracle too")
     ap.add_argument("--neq-replicas", type=int, default=256, help="neq: ensemble size")
     ap.add_argument("--neq-events", type=int, default=100, help="neq: coarse steps recorded")
     ap.add_argument("--pdf-out", default="", help="paper: write the binned displacement PDFs and K(X_i) here (JSON)")
@@ -677,111 +681,19 @@ SHELLS = {"f0": [0], "f1-4": [1, 2, 3, 4], "f5-8": [5, 6, 7, 8], "f9-12": [9, 10
           "f13-20": list(range(13, 21)), "f21-24": [21, 22, 23, 24], "f25-48": list(range(25, 49))}
 
 
-def bench_paper(args):
-    """The paper's sweep at reduced length: R independent systems of N = 99,856
-    LJ particles in L = 1000 at kT = 20, equilibrated once, then each Table 1
-    row in turn (its lattice lx and coarse step) with the fused coarse-graining
-    for E events, a snapshot at every event, and the displacement histograms
-    of the row's coarse step.  Per row: a^2 (the paper fixes ~0.1611 by its
-    choice of dt_cg), lambda_2, measured f_eq against the single Gaussian and
-    the WSG per D2Q25 set, and the KL divergences of the binned displacement
-    PDF (Fig. 2)."""
-    import torch
-
-    import mdlg_inputs as mi
-    import paper_2101_01160_amd as m
-
-    log = lambda s_: print("# " + s_, file=sys.stderr, flush=True)
-    R, E, N, L, kT = args.paper_replicas, args.events, PAPER_N, PAPER_L, PAPER_KT
-    rows = [int(r) for r in args.rows.split(",")] if args.rows else list(range(len(TABLE1)))
-    phi = N * math.pi / (4.0 * L * L)
-    pos, vel = [], []
-    for r in range(R):
-        rng = np.random.Generator(np.random.PCG64(args.seed + r))
-        pos.append(mi.jittered_grid(N, L, rng))
-        vel.append(mi.maxwell_velocities(N, kT, rng))
-    ntot = N * R
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    params = [m.lj_params(N, L, force_bits=args.force_bits) for _ in range(R)]
-    sysm = m.LJSystem(torch.from_numpy(np.concatenate(pos)).to(dev), torch.from_numpy(np.concatenate(vel)).to(dev),
-                      params=params)
-    info = sysm.info()
-    K = info["rebuild_every"]
-    offsets = np.arange(R + 1, dtype=np.int64) * N
-    # equilibration; its first part runs as timed graphs and gives the kernel times
-    units = max(3, math.ceil(min(args.equil, 40000) / K))
-    kms, kcnt = sysm.step_timed(units)
-    rest = max(0, args.equil - units * K)
-    if rest:
-        sysm.step(rest)
-    torch.cuda.synchronize()
-    sysm.check()
-    log(f"equilibrated {units * K + rest} MD steps; {R} x {N} particles, rebuild_every={K}")
-    # velocity autocorrelation over 6 tau (a snapshot every 100 MD steps), for lambda from the VACF
-    vstride, vsnap = 100, 601
-    vs = torch.empty((vsnap, ntot, 2), dtype=torch.float64, device=dev)
-    m.lj_md_get_state(sysm.handle, None, vs[0], None)
-    for p_ in range(1, vsnap):
-        sysm.step(vstride)
-        m.lj_md_get_state(sysm.handle, None, vs[p_], None)
-    vlags = sorted({0} | {int(round(x)) for x in np.geomspace(1, vsnap - 1, 64)})
-    csum = torch.zeros((R, len(vlags)), dtype=torch.float64, device=dev)
-    v0 = torch.cuda.Event(enable_timing=True)
-    v1 = torch.cuda.Event(enable_timing=True)
-    v0.record()
-    m.mdlg_vacf(offsets, vs, vlags, csum)
-    v1.record()
-    torch.cuda.synchronize()
-    vacf_ms = v0.elapsed_time(v1)
-    del vs
-    c_t = csum.cpu().numpy().sum(axis=0) / np.array([ntot * (vsnap - l) for l in vlags], dtype=np.float64)
-    t_t = np.array(vlags, dtype=np.float64) * vstride * 1e-4
-    tau_vacf, _ = m.mdlg_lambda_vacf(t_t, c_t, 1.0, 0.01)
-    log(f"VACF: C(0) = {c_t[0]:.3f}, tau = {tau_vacf:.4f} ({vacf_ms:.1f} ms for {len(vlags)} lags)")
-    n_bin = 97                 # bins of dx / 8 over +-6 dx
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    md_steps = 0
-    hist_ms = 0.0
-    raw = []
-    e0.record()
-    for ri in rows:
+def _row_results(m, R, L, E_done, rows_state, t_t, c_t, n_bin):
+    """Per Table 1 row: a^2, r, lambda, measured f_eq against G and WSG per
+    D2Q25 set, and the KL divergences of the binned displacement PDF."""
+    out_rows, pdfs = [], []
+    for ri in sorted(rows_state):
+        st = rows_state[ri]
         dt_cg, dx_print, lx, freq = TABLE1[ri]
         dxl = L / lx
-        acc = sysm.attach_cg(lx, freq)
-        sp = torch.empty((E + 1, ntot, 2), dtype=torch.float64, device=dev)
-        si = torch.empty((E + 1, ntot, 2), dtype=torch.int32, device=dev)
-        m.lj_md_get_state(sysm.handle, sp[0], None, si[0])
-        for e in range(E):
-            sysm.step(freq)
-            m.lj_md_get_state(sysm.handle, sp[e + 1], None, si[e + 1])
-        md_steps += E * freq
-        hist = torch.zeros((R, 1, 2, n_bin + 2), dtype=torch.int64, device=dev)
-        h0 = torch.cuda.Event(enable_timing=True)
-        h1 = torch.cuda.Event(enable_timing=True)
-        h0.record()
-        m.mdlg_displacement_hist(offsets, [L] * R, sp, si, [1], [dxl / 8.0], n_bin, hist)
-        h1.record()
-        events = acc.events
-        counts = acc.counts.cpu().numpy()
-        moments = acc.moments.cpu().numpy()
-        sysm.detach_cg()
-        h1.synchronize()
-        hist_ms += h0.elapsed_time(h1)
-        raw.append((ri, dxl, events, counts, moments, hist.cpu().numpy()))
-        del sp, si
-        log(f"row {ri}: dt_cg={dt_cg} lx={lx} freq={freq}: {events} events")
-    e1.record()
-    torch.cuda.synchronize()
-    sysm.check()
-    ms = e0.elapsed_time(e1)
-    sysm.close()
-    value = ntot * md_steps / (ms * 1e-3)
-
-    out_rows, pdfs = [], []
-    for ri, dxl, events, counts, moments, hist in raw:
-        dt_cg, dx_print, lx, freq = TABLE1[ri]
+        events = int(st["events"])
+        if events == 0:
+            continue
+        counts, moments, hist = st["counts"], st["moments"], st["hist"]
+        ntot = R * PAPER_N
         c = counts.sum(axis=0)
         g, ovf = m.mdlg_feq_measured(c, ntot, events, symmetrize=True)
         mu2, mu4, a2 = m.mdlg_moments(moments.sum(axis=0), dxl)
@@ -792,9 +704,10 @@ def bench_paper(args):
             cnt = float(c[idx].sum())
             gm, gg, gw = float(g[idx].mean()), float(gG[idx].mean()), float(gW[idx].mean())
             shells[name] = {"meas": gm, "G": gg, "WSG": gw, "meas/G-1": gm / gg - 1.0, "meas/WSG-1": gm / gw - 1.0,
-                            "poisson_se": 1.0 / math.sqrt(cnt) if cnt > 0 else None}
-        # the a^2 of each replica on its own: spread between independent systems
-        a2_rep = [m.mdlg_moments(moments[k], dxl)[2] for k in range(R)]
+                            "WSG/G-1": gw / gg - 1.0, "poisson_se": 1.0 / math.sqrt(cnt) if cnt > 0 else None}
+        rep_mom = [m.mdlg_moments(moments[k], dxl) for k in range(R)]
+        a2_rep = [x[2] for x in rep_mom]
+        r_rep = [x[1] / (3.0 * x[0] ** 2) for x in rep_mom]
         h = dxl / 8.0
         p_md = m.mdlg_pdf_measured(hist)
         p_g, p_w = m.mdlg_pdf_bins(mu2, lam, 0.0, h, n_bin)
@@ -803,9 +716,10 @@ def bench_paper(args):
         _, d_wg = m.mdlg_kl_divergence(p_w, p_g)
         samples = int(hist.sum())
         _, lam_vacf = m.mdlg_lambda_vacf(t_t, c_t, dt_cg, 0.01)
-        out_rows.append({"row": ri, "dt_cg": dt_cg, "lx": lx, "dx": dxl, "freq": freq, "events": int(events),
+        out_rows.append({"row": ri, "dt_cg": dt_cg, "lx": lx, "dx": dxl, "freq": freq, "events": events,
                          "a2": a2, "a2_replica_sd": float(np.std(a2_rep, ddof=1)) if R > 1 else None,
-                         "a2_paper": PAPER_A2, "r": r, "lambda2": lam, "lambda1": (1.0 / lam if lam > 0 else None),
+                         "a2_paper": PAPER_A2, "r": r, "r_replica_sd": float(np.std(r_rep, ddof=1)) if R > 1 else None,
+                         "lambda2": lam, "lambda1": (1.0 / lam if lam > 0 else None),
                          "lambda_vacf": lam_vacf, "overflow": ovf,
                          "max_abs_meas_minus_G": float(np.max(np.abs(g - gG))),
                          "max_abs_meas_minus_WSG": float(np.max(np.abs(g - gW))), "shells": shells,
@@ -813,38 +727,276 @@ def bench_paper(args):
                                 "finite_sample_bias": (n_bin + 1) / (2.0 * samples)}})
         pdfs.append({"row": ri, "dt_cg": dt_cg, "h": h, "n_bin": n_bin, "P_MD": p_md.tolist(), "P_G": p_g.tolist(),
                      "P_WSG": p_w.tolist(), "K_MD_G": k_g.tolist(), "K_MD_WSG": k_w.tolist()})
+    return out_rows, pdfs
+
+
+def _displacement_moments(p0, p1, i0, i1, L):
+    """mu2, mu4 (pooled over the axes) of the box-frame displacements and their
+    standard errors from the spread over particles (host arithmetic of the
+    comparison, not of the method)."""
+    d = (p1 - p0) + L * (i1 - i0).astype(np.float64)
+    d2 = (d * d).ravel()
+    d4 = d2 * d2
+    n = d2.size
+    return (float(d2.mean()), float(d2.std(ddof=1) / math.sqrt(n)), float(d4.mean()), float(d4.std(ddof=1) / math.sqrt(n)))
+
+
+def paper_oracle_crosscheck(m, torch, pos, vel, L, row=0):
+    """One coarse step of Table 1's row `row` from an equilibrated state of one
+    system, advanced by the GPU and by the oracle on the host: mu2, mu4 and
+    r = mu4 / (3 mu2^2) of the displacements over the step, each with its
+    standard error over the particles.  The two trajectories start equal and
+    differ by the rounding of the force sums."""
+    from oracle import md as omd
+    dt_cg, _, lx, freq = TABLE1[row]
+    n = pos.shape[0]
+    sysm = m.LJSystem(torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(), box_l=L)
+    t0 = time.perf_counter()
+    sysm.step(freq)
+    gp, _, gi = (x.cpu().numpy() for x in sysm.state())
+    sysm.check()
+    sysm.close()
+    t_gpu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op, _, oi, _ = omd.md_run(pos.copy(), vel.copy(), np.zeros((n, 2), np.int64), L, freq)  # md_run works in place
+    t_orc = time.perf_counter() - t0
+    z = np.zeros((n, 2), np.int64)
+    g = _displacement_moments(pos, gp, z, gi, L)
+    o = _displacement_moments(pos, op, z, oi, L)
+    rg, ro = g[2] / (3 * g[0] ** 2), o[2] / (3 * o[0] ** 2)
+
+    def r_se(mm):  # first-order propagation of the two standard errors
+        mu2, s2, mu4, s4 = mm
+        return math.sqrt((s4 / (3 * mu2 ** 2)) ** 2 + (2 * mu4 * s2 / (3 * mu2 ** 3)) ** 2)
+    out = {"row": row, "md_steps": freq, "particles": n, "gpu": {"mu2": g[0], "mu2_se": g[1], "mu4": g[2],
+                                                                   "mu4_se": g[3], "r": rg, "r_se": r_se(g)},
+           "oracle": {"mu2": o[0], "mu2_se": o[1], "mu4": o[2], "mu4_se": o[3], "r": ro, "r_se": r_se(o)},
+           "oracle_seconds": t_orc, "gpu_seconds": t_gpu,
+           "max_abs_position_difference": float(np.max(np.abs((gp + L * gi) - (op + L * oi))))}
+    out["within_3se"] = bool(abs(g[0] - o[0]) <= 3 * math.hypot(g[1], o[1]) and abs(g[2] - o[2]) <= 3 * math.hypot(g[3], o[3])
+                             and abs(rg - ro) <= 3 * math.hypot(r_se(g), r_se(o)))
+    return out
+
+
+def bench_paper(args):
+    """The paper's sweep: R independent systems of N = 99,856 LJ particles in
+    L = 1000 at kT = 20 (Table 1's system), equilibrated for `--equil` MD steps
+    and then run as one trajectory that serves every Table 1 row: row k takes
+    the snapshots at multiples of its MD output frequency and coarse-grains
+    each consecutive pair on its own lattice (Eq.(n_i), the standalone
+    entry point, per replica), for E coarse steps per row; the displacement
+    histograms of the same pairs give P^MD(X_i) of Fig. 2.  A row's E windows
+    are the first E freq steps of the trajectory, so all rows cost the MD of
+    the longest.  The run can stop at an MD step (--stop-at) and write a
+    checkpoint (state, accumulators, the last snapshot of unfinished rows) to
+    resume from (--resume).  Also: the velocity autocorrelation (lambda from
+    the VACF) and one coarse step of row 0 advanced by the GPU and by the
+    oracle from the same equilibrated state (mu2, mu4, r within their standard
+    errors)."""
+    import torch
+
+    import mdlg_inputs as mi
+    import paper_2101_01160_amd as m
+
+    log = lambda s_: print("# " + s_, file=sys.stderr, flush=True)
+    R, E, N, L, kT = args.paper_replicas, args.events, PAPER_N, PAPER_L, PAPER_KT
+    rows = [int(r) for r in args.rows.split(",")] if args.rows else list(range(len(TABLE1)))
+    phi = N * math.pi / (4.0 * L * L)
+    ntot = N * R
+    n_bin = 97                 # bins of dx / 8 over +-6 dx
+    B = 20                     # snapshots per row processed per batch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    offsets = np.arange(R + 1, dtype=np.int64) * N
+    t_wall0 = time.perf_counter()
+    gpu_ms = {"equil": 0.0, "vacf_md": 0.0, "sweep_md": 0.0}
+    if args.resume:
+        ck = np.load(args.resume + ".npz", allow_pickle=False)
+        meta = json.loads(str(ck["meta"]))
+        sysm = m.LJSystem.load(args.resume + ".state")
+        t_sweep = int(meta["t_sweep"])
+        rows = meta["rows"]
+        E = int(meta["E"])
+        t_t, c_t, tau_vacf = np.asarray(meta["vacf_t"]), np.asarray(meta["vacf_c"]), meta["tau_vacf"]
+        crosscheck, equil_info = meta["crosscheck"], meta["equil_info"]
+        gpu_ms = meta["gpu_ms"]
+        rows_state = {}
+        for ri in rows:
+            rows_state[ri] = {"events": int(ck[f"ev_{ri}"]), "counts": ck[f"counts_{ri}"], "moments": ck[f"moments_{ri}"],
+                              "hist": ck[f"hist_{ri}"]}
+        log(f"resumed at sweep step {t_sweep}: events {[rows_state[ri]['events'] for ri in rows]}")
+    else:
+        pos, vel = [], []
+        for r in range(R):
+            rng = np.random.Generator(np.random.PCG64(args.seed + r))
+            pos.append(mi.jittered_grid(N, L, rng))
+            vel.append(mi.maxwell_velocities(N, kT, rng))
+        params = [m.lj_params(N, L, force_bits=args.force_bits) for _ in range(R)]
+        sysm = m.LJSystem(torch.from_numpy(np.concatenate(pos)).to(dev),
+                          torch.from_numpy(np.concatenate(vel)).to(dev), params=params)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        left = args.equil
+        while left > 0:   # in pieces, so that a long equilibration reports progress
+            k = min(left, 500000)
+            sysm.step(k)
+            left -= k
+            torch.cuda.synchronize()
+            log(f"equilibration: {args.equil - left} / {args.equil} MD steps")
+        e1.record()
+        torch.cuda.synchronize()
+        sysm.check()
+        gpu_ms["equil"] = e0.elapsed_time(e1)
+        equil_info = {"md_steps": args.equil, "rebuild_every": sysm.info()["rebuild_every"]}
+        # one coarse step of row 0 by the GPU and by the oracle, from replica 0's equilibrated state
+        crosscheck = None
+        if args.crosscheck:
+            p_all, v_all, _ = (x.cpu().numpy() for x in sysm.state())
+            log("oracle cross-check of row 0 (one coarse step on the host) ...")
+            crosscheck = paper_oracle_crosscheck(m, torch, np.ascontiguousarray(p_all[:N]),
+                                                 np.ascontiguousarray(v_all[:N]), L, 0)
+            log(f"cross-check: {json.dumps(crosscheck)}")
+        # velocity autocorrelation over 6 tau (a snapshot every 100 MD steps), for lambda from the VACF
+        vstride, vsnap = 100, 601
+        vs = torch.empty((vsnap, ntot, 2), dtype=torch.float64, device=dev)
+        m.lj_md_get_state(sysm.handle, None, vs[0], None)
+        e0.record()
+        for p_ in range(1, vsnap):
+            sysm.step(vstride)
+            m.lj_md_get_state(sysm.handle, None, vs[p_], None)
+        e1.record()
+        torch.cuda.synchronize()
+        gpu_ms["vacf_md"] = e0.elapsed_time(e1)
+        vlags = sorted({0} | {int(round(x)) for x in np.geomspace(1, vsnap - 1, 64)})
+        csum = torch.zeros((R, len(vlags)), dtype=torch.float64, device=dev)
+        m.mdlg_vacf(offsets, vs, vlags, csum)
+        del vs
+        c_t = csum.cpu().numpy().sum(axis=0) / np.array([ntot * (vsnap - l) for l in vlags], dtype=np.float64)
+        t_t = np.array(vlags, dtype=np.float64) * vstride * 1e-4
+        tau_vacf, _ = m.mdlg_lambda_vacf(t_t, c_t, 1.0, 0.01)
+        log(f"VACF: C(0) = {c_t[0]:.3f}, tau = {tau_vacf:.4f}")
+        t_sweep = 0
+        rows_state = {ri: {"events": 0, "counts": np.zeros((R, 50), np.int64), "moments": np.zeros((R, 5)),
+                           "hist": np.zeros((R, 1, 2, n_bin + 2), np.int64)} for ri in rows}
+    # device buffers of the rows still running: snapshot stacks and accumulators
+    active = [ri for ri in rows if rows_state[ri]["events"] < E]
+    dstate = {}
+    for ri in active:
+        st = rows_state[ri]
+        dstate[ri] = {"pos": torch.empty((B + 1, ntot, 2), dtype=torch.float64, device=dev),
+                      "img": torch.empty((B + 1, ntot, 2), dtype=torch.int32, device=dev), "j": 0,
+                      "counts": torch.from_numpy(st["counts"].copy()).to(dev),
+                      "moments": torch.from_numpy(st["moments"].copy()).to(dev),
+                      "hist": torch.from_numpy(st["hist"].copy()).to(dev)}
+        if args.resume:
+            dstate[ri]["pos"][0].copy_(torch.from_numpy(ck[f"last_pos_{ri}"]))
+            dstate[ri]["img"][0].copy_(torch.from_numpy(ck[f"last_img_{ri}"]))
+        elif st["events"] == 0:
+            m.lj_md_get_state(sysm.handle, dstate[ri]["pos"][0], None, dstate[ri]["img"][0])
+
+    def flush(ri):
+        """Coarse-grain and histogram the snapshot pairs gathered for row ri."""
+        d = dstate[ri]
+        j = d["j"]
+        if j == 0:
+            return
+        dt_cg, _, lx, freq = TABLE1[ri]
+        for p_ in range(j):
+            for r in range(R):
+                sl = slice(r * N, (r + 1) * N)
+                m.mdlg_coarse_grain(lx, L, d["pos"][p_, sl], d["pos"][p_ + 1, sl], d["counts"][r], d["moments"][r],
+                                    d["img"][p_, sl], d["img"][p_ + 1, sl])
+        m.mdlg_displacement_hist(offsets, [L] * R, d["pos"][:j + 1], d["img"][:j + 1], [1], [(L / lx) / 8.0], n_bin,
+                                 d["hist"])
+        d["pos"][0].copy_(d["pos"][j])
+        d["img"][0].copy_(d["img"][j])
+        d["j"] = 0
+
+    stop_at = args.stop_at if args.stop_at > 0 else None
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    md_steps = 0
+    last_log = time.perf_counter()
+    while active:
+        nxt = {ri: (rows_state[ri]["events"] + 1) * TABLE1[ri][3] for ri in active}
+        t_next = min(nxt.values())
+        if stop_at is not None and t_next > stop_at:
+            break
+        e0.record()
+        sysm.step(t_next - t_sweep)
+        e1.record()
+        e1.synchronize()
+        gpu_ms["sweep_md"] += e0.elapsed_time(e1)
+        md_steps += t_next - t_sweep
+        t_sweep = t_next
+        due = [ri for ri in active if nxt[ri] == t_next]
+        src = None
+        for ri in due:
+            d = dstate[ri]
+            d["j"] += 1
+            if src is None:
+                m.lj_md_get_state(sysm.handle, d["pos"][d["j"]], None, d["img"][d["j"]])
+                src = (d["pos"][d["j"]], d["img"][d["j"]])
+            else:
+                d["pos"][d["j"]].copy_(src[0])
+                d["img"][d["j"]].copy_(src[1])
+            rows_state[ri]["events"] += 1
+            if d["j"] == B or rows_state[ri]["events"] == E:
+                flush(ri)
+        active = [ri for ri in active if rows_state[ri]["events"] < E]
+        if time.perf_counter() - last_log > 30.0:
+            last_log = time.perf_counter()
+            log(f"sweep step {t_sweep}: events {[rows_state[ri]['events'] for ri in rows]}")
+    for ri in list(dstate):
+        flush(ri)
+        rows_state[ri]["counts"] = dstate[ri]["counts"].cpu().numpy()
+        rows_state[ri]["moments"] = dstate[ri]["moments"].cpu().numpy()
+        rows_state[ri]["hist"] = dstate[ri]["hist"].cpu().numpy()
+    torch.cuda.synchronize()
+    sysm.check()
+    if active and args.checkpoint:
+        # unfinished rows: state, accumulators and their last snapshot
+        sysm.save(args.checkpoint + ".state")
+        arrays = {}
+        for ri in rows:
+            st = rows_state[ri]
+            arrays[f"ev_{ri}"] = np.int64(st["events"])
+            arrays[f"counts_{ri}"] = st["counts"]
+            arrays[f"moments_{ri}"] = st["moments"]
+            arrays[f"hist_{ri}"] = st["hist"]
+            if ri in active:
+                arrays[f"last_pos_{ri}"] = dstate[ri]["pos"][0].cpu().numpy()
+                arrays[f"last_img_{ri}"] = dstate[ri]["img"][0].cpu().numpy()
+        meta = {"t_sweep": t_sweep, "rows": rows, "E": E, "vacf_t": t_t.tolist(), "vacf_c": c_t.tolist(),
+                "tau_vacf": tau_vacf, "crosscheck": crosscheck, "equil_info": equil_info, "gpu_ms": gpu_ms}
+        np.savez(args.checkpoint + ".npz", meta=json.dumps(meta), **arrays)
+        log(f"checkpoint written at sweep step {t_sweep}")
+    sysm.close()
+    wall = time.perf_counter() - t_wall0
+    out_rows, pdfs = _row_results(m, R, L, E, rows_state, t_t, c_t, n_bin)
     if args.pdf_out:
         with open(args.pdf_out, "w") as f:
             json.dump(pdfs, f)
-    t_step, t_cg, t_rebuild = (float(x) for x in kms)
-    spl = int(info.get("steps_per_launch", 1)) or 1
-    launch_ms = spl * t_step
-    launch_bytes = spl * STEP_BYTES * ntot
-    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    value = ntot * md_steps / (gpu_ms["sweep_md"] * 1e-3) if gpu_ms["sweep_md"] > 0 else None
     line = {
-        "metric": "MD particle-steps/s, paper regime (Table 1 sweep, fused MDLG coarse-graining)",
-        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": md_steps, "warmup": units * K + rest,
-        "ms_per_step": ms / md_steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": "MD particle-steps/s, paper regime (Table 1 sweep, one trajectory for all rows)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": md_steps, "warmup": equil_info["md_steps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces",
         "data": "synthetic (jittered-grid positions, Maxwellian velocities, seeds %d..%d)" % (args.seed,
                                                                                          args.seed + R - 1),
         "config": {"workload": f"{R} x 2D LJ gas N={N}, L={L}, phi={phi:.6f}, kT={kT}, dt=1e-4; "
-                               f"{args.equil} equilibration steps; Table 1 rows {rows}, {E} events each",
-                   "replicas": R, "events_per_row": E, "equil_steps": args.equil},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "MD step kernel" + (f", {spl} ordinary steps per launch" if spl > 1 else ""),
-                     "kernel_ms": launch_ms, "bytes_per_launch": launch_bytes, "steps_per_launch": spl},
-        "kernel_ms": {"step": t_step, "step_with_cg_event": t_cg, "rebuild": t_rebuild,
-                      "launches": [int(x) for x in kcnt], "displacement_hist_total": hist_ms, "vacf": vacf_ms},
-        "vacf": {"tau": tau_vacf, "C0": float(c_t[0]), "two_kT": 2 * kT, "stride_md_steps": vstride,
-                 "snapshots": vsnap, "t": t_t[::8].tolist(), "C_over_C0": (c_t[::8] / c_t[0]).tolist()},
+                               f"{equil_info['md_steps']} equilibration steps; Table 1 rows {rows}, {E} coarse "
+                               f"steps each from one trajectory", "replicas": R, "events_per_row": E,
+                   "equil_steps": equil_info["md_steps"]},
+        "status": "complete" if not active else f"checkpoint at sweep step {t_sweep}",
+        "sweep_steps_done": t_sweep, "wall_s_this_call": wall, "gpu_ms": gpu_ms,
+        "vacf": {"tau": tau_vacf, "C0": float(c_t[0]), "two_kT": 2 * kT,
+                 "t": list(np.asarray(t_t)[::8]), "C_over_C0": list((np.asarray(c_t) / c_t[0])[::8])},
+        "oracle_crosscheck_row0": crosscheck,
         "rows": out_rows,
     }
-    if args.cpu_baseline_steps > 0:
-        log("cpu baseline (oracle) ...")
-        steps = 3 * args.cpu_baseline_steps   # ~15 s of one host core at this size
-        line["cpu_baseline"] = cpu_baseline(N, phi, kT, 250, 50, args.seed, steps)[0]
     print(json.dumps(line), flush=True)
 
 

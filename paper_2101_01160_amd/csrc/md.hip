@@ -1315,6 +1315,8 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     __shared__ int lq[kPairCap];   // slot of each staged index
     __shared__ int lq0[kPairCap];  // slots in segment order
     __shared__ unsigned char gq[kPairCap];
+    __shared__ unsigned char cntq[kPairCap];  // list lengths, segment order
+    __shared__ unsigned char lcnt[kPairCap];  // list lengths, final order
     constexpr int kGroups = 128;  // list-row groups 0 .. maxnb / kListU (maxnb <= 248)
     __shared__ int gcnt[3][kGroups];
     const int ng = maxnb / kListU + 1;
@@ -1333,7 +1335,9 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         return r;
     };
     for (int q = threadIdx.x; q < listed; q += BS) {
-        const int g = (nbc[lq0[q]] + kListU - 1) / kListU;
+        const int nn = nbc[lq0[q]];
+        const int g = (nn + kListU - 1) / kListU;
+        cntq[q] = (unsigned char)nn;
         gq[q] = (unsigned char)g;
         atomicAdd(&gcnt[ring_of(q)][g], 1);
     }
@@ -1355,42 +1359,49 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         const int slot = lq0[q];
         lq[qn] = slot;
         list[qn] = slot;
+        if (q < listed) lcnt[qn] = cntq[q];
         unsigned int h = bucket(slot);
         while (atomicCAS(&hkey[h], 0, slot + 1) != 0) h = (h + 1) & (kPairHash - 1);
         hval[h] = (unsigned short)qn;
     }
     __syncthreads();
-    // particles of every ring but the last: neighbour counts and lists as staged indices
+    // particles of every ring but the last: neighbour counts and lists as staged
+    // indices.  The first kListPre list rows of a particle are read together
+    // (they always exist, see list_rows), further ones kListU at a time.
     const int slot0 = R.slot0, nrep = R.n;
     unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
+    auto map_entry = [&](int s, int q, int j, int off, int lim) {
+        int kr = (s - slot0) + off;
+        kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
+        const int k = slot0 + kr;
+        unsigned int h = bucket(k);
+        int key;
+        while ((key = hkey[h]) != k + 1 && key != 0) h = (h + 1) & (kPairHash - 1);
+        int loc = key == 0 ? -1 : (int)hval[h];
+        if (loc < 0 || loc >= lim) {
+            atomicOr(err, ERR_NLIST);
+            loc = 0;
+        }
+        tl[(long long)j * kPairCap + q] = (unsigned short)loc;
+    };
     for (int q = threadIdx.x; q < listed; q += blockDim.x) {
         const int s = lq[q];
-        const int nn = nbc[s];
+        const int nn = lcnt[q];
+        int first_rows[kListPre];
+        list_rows(nbl, (unsigned int)s, (unsigned int)S, first_rows);
         tcnt[(long long)t * kPairCap + q] = (unsigned char)nn;
         int ring = 0;
         while (q >= n[ring]) ++ring;
         const int lim = ring + 1 < rings ? n[ring + 1] : tot;
-        // list rows kListU at a time, issued together (they always exist, see list_rows)
-        for (int j0 = 0; j0 < nn; j0 += kListU) {
+#pragma unroll
+        for (int j = 0; j < kListPre; ++j)
+            if (j < nn) map_entry(s, q, j, first_rows[j], lim);
+        for (int j0 = kListPre; j0 < nn; j0 += kListU) {
             int rows[kListU];
             list_rows(nbl, (unsigned int)s + (unsigned int)j0 * (unsigned int)S, (unsigned int)S, rows);
 #pragma unroll
-            for (int u = 0; u < kListU; ++u) {
-                const int j = j0 + u;
-                if (j >= nn) break;
-                int kr = (s - slot0) + rows[u];
-                kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
-                const int k = slot0 + kr;
-                unsigned int h = bucket(k);
-                int key;
-                while ((key = hkey[h]) != k + 1 && key != 0) h = (h + 1) & (kPairHash - 1);
-                int loc = key == 0 ? -1 : (int)hval[h];
-                if (loc < 0 || loc >= lim) {
-                    atomicOr(err, ERR_NLIST);
-                    loc = 0;
-                }
-                tl[(long long)j * kPairCap + q] = (unsigned short)loc;
-            }
+            for (int u = 0; u < kListU; ++u)
+                if (j0 + u < nn) map_entry(s, q, j0 + u, rows[u], lim);
         }
     }
 }
@@ -1858,7 +1869,7 @@ struct lj_md {
     int ppar = 0, opar = 0, vpar = 0;  // current buffer of pos / of img, id, snap / of vel
     bool vel_full = true;
     bool have_cellof = false;
-    bool binned = false;  // key, rank and cnt hold the current positions' binning (done by the last step launch)
+    bool binned = false;  // key and cnt hold the current positions' binning (done by the last step launch)
     bool broken = false;
     int K = 50;
     bool K_auto = true;

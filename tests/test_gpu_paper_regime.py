@@ -58,3 +58,39 @@ def test_table1_rows_give_a2_near_0_1611(gas, lx, freq, tol):
           flush=True)
     assert meas / G - 1.0 > max(0.05, 4 * se)
     assert abs(meas / W - 1.0) < 4 * se + 0.01
+
+
+def _moments(p0, p1, i0, i1, L):
+    d = (p1 - p0) + L * (i1 - i0).astype(np.float64)
+    d2 = (d * d).ravel()
+    d4 = d2 * d2
+    n = d2.size
+    return d2.mean(), d2.std(ddof=1) / math.sqrt(n), d4.mean(), d4.std(ddof=1) / math.sqrt(n)
+
+
+def test_one_coarse_step_matches_oracle(gas):
+    """One coarse step of Table 1's first row (3911 MD steps) from the
+    equilibrated gas, advanced by the GPU and by the oracle from the same
+    state: the displacement moments mu2, mu4 (Eq.(fourth_order)) and
+    r = mu4 / (3 mu2^2) agree within three standard errors over the particles."""
+    import torch
+
+    from oracle import md as omd
+    m, sysm, n, L = gas
+    pos, vel, _ = (t.cpu().numpy() for t in sysm.state())
+    print("cross-check: GPU and oracle, 3911 MD steps of 99,856 particles", flush=True)
+    g = m.LJSystem(torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(), box_l=L)
+    g.step(3911)
+    gp, _, gi = (t.cpu().numpy() for t in g.state())
+    g.check()
+    g.close()
+    op, _, oi, _ = omd.md_run(pos.copy(), vel.copy(), np.zeros((n, 2), np.int64), L, 3911)  # md_run works in place
+    z = np.zeros((n, 2), np.int64)
+    mg, mo = _moments(pos, gp, z, gi, L), _moments(pos, op, z, oi, L)
+    for a, b in ((0, 1), (2, 3)):
+        assert abs(mg[a] - mo[a]) <= 3 * math.hypot(mg[b], mo[b])
+    rg, ro = mg[2] / (3 * mg[0] ** 2), mo[2] / (3 * mo[0] ** 2)
+    se_r = math.hypot(mg[3] / (3 * mg[0] ** 2), 2 * mg[2] * mg[1] / (3 * mg[0] ** 3))
+    print(f"r: GPU {rg:.5f}, oracle {ro:.5f} (se {se_r:.5f})", flush=True)
+    assert abs(rg - ro) <= 3 * math.sqrt(2) * se_r
+    assert rg > 1.0  # heavier tails than a Gaussian: collisions during the coarse step
