@@ -48,6 +48,7 @@ typedef int32_t mdlg_status;
 #define MDLG_ESKIN (-5)       /* a particle drifted past the cell-list skin      */
 #define MDLG_ENOTIMPL (-6)    /* feature not available in this library           */
 #define MDLG_ECAPACITY (-7)   /* a neighbour list or a fused-step tile overflowed its capacity */
+#define MDLG_ERANGE (-8)      /* a parameter point outside the range a fitted table covers */
 
 #define MDLG_NQ 49            /* D2Q49 lattice velocities, |v_x|, |v_y| <= 3     */
 #define MDLG_HIST_MAX_BINS 4094 /* displacement-histogram bins (2 more count the tails) */
@@ -465,7 +466,10 @@ mdlg_status mdlg_kl_divergence(const double* r, const double* q, int32_t n, doub
  * g_i = f_i^eq / rho of the D2Q49 equilibrium (Eq.(theory_feq)):
  *   h1 = silu(x' W1 + b1), h2 = silu(h1 W2 + b2), h3 = silu(h2 W3 + b3),
  *   g = softmax(h3 W4 + b4),  widths 6 -> 256 -> 256 -> 256 -> 49,
- * with the fixed input scaling x' = x * (1/0.4, 1/20, 100, 1/0.2, 1, 1).
+ * with the fixed input map x' = (phi / 0.4, ln kT / ln 20, (ln(dt_cg/dx) + 6) / 1.5,
+ * 5 |u| cos, 5 |u| sin, 5 |u|) (fp32; logarithms of the two scales, whose
+ * product kT (dt_cg/dx)^2 is a^2 in the ballistic limit; the drift as a
+ * vector, so that the lattice's reflection symmetries are linear in it).
  * It is trained on measured f_eq with the Kullback-Leibler divergence of
  * Eq.(kullback_leibler), sum_i R_i log(R_i / g_i) averaged over the batch,
  * as the loss, by Adam (beta1 0.9, beta2 0.999, eps 1e-8).
@@ -508,6 +512,46 @@ mdlg_status mdlg_feq_surrogate(mdlg_mlp* mlp, const double* x, double a2, double
                                double* g_out, int32_t* used_fallback, double* err, void* stream);
 /* Release the handle and its device memory (NULL is ignored). */
 void mdlg_mlp_destroy(mdlg_mlp* mlp);
+
+/* Displacement moments without a trajectory: the Poisson-WSG guard above
+ * needs a^2 (Eq.(theory_a)) and lambda (Eq.(lambda_eq)), which the method
+ * measures.  A moment table fits them over the training runs' parameter
+ * points so that the guard needs no molecular dynamics.  Fields ln a^2 and
+ * r = mu4 / (3 mu2^2) are fitted on a regular grid of dims[0] x dims[1] x
+ * dims[2] nodes spanning the samples' range of the coordinates
+ * (phi, ln kT, ln(dt_cg/dx)) by least squares with multilinear hat functions
+ * plus smooth * n / P times the sum of squared second differences along each
+ * axis (node units; zero for any multilinear function, which the fit thus
+ * reproduces exactly); evaluation interpolates multilinearly and takes
+ * lambda from r on the given root branch (as mdlg_lambda_from_moments).
+ * Host-only, FP64; the handle owns host memory only. */
+typedef struct mdlg_moment_table mdlg_moment_table;
+
+/* samples host [n][5] = (phi, kT, dt_cg/dx, a2, r) with kT, dt_cg/dx, a2 > 0;
+ * dims host [3], each in [1, 64], product <= 2048 (an axis whose samples do
+ * not spread needs dims 1); smooth >= 0 (0 only when samples reach every
+ * node); branch 1 or 2.  Errors: EINVAL (arguments, or a singular fit). */
+mdlg_status mdlg_moment_table_create(mdlg_moment_table** out, const double* samples, int64_t n,
+                                     const int32_t* dims, double smooth, int32_t branch);
+/* x host [3] = (phi, kT, dt_cg/dx) -> a2, lambda and r (each may be NULL).
+ * ERANGE when x lies outside the fitted range (the samples' bounding box). */
+mdlg_status mdlg_moment_table_eval(const mdlg_moment_table* table, const double* x, double* a2,
+                                   double* lambda, double* r);
+/* The grid: dims [3], coordinate bounds lo/hi [3] (phi, ln kT, ln(dt_cg/dx))
+ * and node values nodes [P][2] = (ln a2, r); any pointer may be NULL. */
+mdlg_status mdlg_moment_table_info(const mdlg_moment_table* table, int32_t* dims, double* lo, double* hi,
+                                   double* nodes);
+/* Release the table (NULL is ignored). */
+void mdlg_moment_table_destroy(mdlg_moment_table* table);
+
+/* mdlg_feq_surrogate with a2 and lambda from the table at (x[0], x[1], x[2])
+ * (the network's phi, kT and dt_cg/dx), so that neither the network nor its
+ * guard needs a trajectory.  a2_out and lambda_out (host, may be NULL)
+ * receive the interpolated moments.  ERANGE outside the table's range (the
+ * caller then measures); otherwise as mdlg_feq_surrogate. */
+mdlg_status mdlg_feq_surrogate_table(mdlg_mlp* mlp, const mdlg_moment_table* table, const double* x,
+                                     double tol, double* g_out, int32_t* used_fallback, double* err,
+                                     double* a2_out, double* lambda_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,7 @@ area fraction phi, temperature kT, coarse time step over lattice spacing
 dt_cg/dx (tau/sigma), the drift |u| (cells per coarse step) and the drift
 direction (cos, sin) — to the 49 D2Q49 equilibrium values g_i = f_i^eq / rho:
 
-    x' = x * SCALE                      (fixed input scaling)
+    x' = encode(x)                      (fixed input map, below)
     h1 = silu(x' W1 + b1)               6 -> 256
     h2 = silu(h1 W2 + b2)               256 -> 256
     h3 = silu(h2 W3 + b3)               256 -> 256
@@ -21,7 +21,26 @@ from __future__ import annotations
 import numpy as np
 
 DIMS = (6, 256, 256, 256, 49)
-SCALE = np.array([1 / 0.4, 1 / 20.0, 100.0, 1 / 0.2, 1.0, 1.0])
+LN20 = float(np.log(20.0))
+
+
+def encode(X, dtype=np.float64):
+    """The network's fixed input map of x = (phi, kT, dt_cg/dx, |u|, cos, sin):
+    (phi / 0.4, ln kT / ln 20, (ln(dt_cg/dx) + 6) / 1.5, 5 |u| cos, 5 |u| sin,
+    5 |u|): logarithms for the two scale variables (in the ballistic limit
+    a^2 = kT (dt_cg/dx)^2, linear in them), the drift as a vector.  dtype
+    float32 evaluates it the way the device does, operation by operation."""
+    X = np.asarray(X, dtype=dtype)
+    f = lambda v: np.asarray(v, dtype=dtype)
+    out = np.empty(X.shape, dtype=dtype)
+    tiny = f(1e-30)
+    out[:, 0] = X[:, 0] * f(2.5)
+    out[:, 1] = np.log(np.maximum(X[:, 1], tiny)) * f(1.0 / LN20)
+    out[:, 2] = (np.log(np.maximum(X[:, 2], tiny)) + f(6.0)) * f(1.0 / 1.5)
+    out[:, 3] = (X[:, 3] * X[:, 4]) * f(5.0)
+    out[:, 4] = (X[:, 3] * X[:, 5]) * f(5.0)
+    out[:, 5] = X[:, 3] * f(5.0)
+    return out
 
 
 def shapes():
@@ -63,7 +82,7 @@ def softmax(z):
 def forward(theta, X):
     """Returns (Q [B,49], cache) for inputs X [B,6] (unscaled)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta)
-    x = np.asarray(X, dtype=np.float64) * SCALE
+    x = encode(X)
     z1 = x @ W1 + b1
     h1 = silu(z1)
     z2 = h1 @ W2 + b2

@@ -34,6 +34,8 @@ __all__ = [
     "mdlg_neq_mdlg", "mdlg_vacf", "mdlg_lambda_vacf", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy", "SurrogateMLP", "MLP_NPARAMS",
+    "mdlg_moment_table_create", "mdlg_moment_table_eval", "mdlg_moment_table_info", "mdlg_moment_table_destroy",
+    "mdlg_feq_surrogate_table", "MomentTable",
 ]
 
 MLP_NPARAMS = _abi.MLP_NPARAMS
@@ -470,6 +472,78 @@ def mdlg_mlp_destroy(h):
     _abi.lib().mdlg_mlp_destroy(h)
 
 
+def mdlg_moment_table_create(samples, dims=(6, 8, 12), smooth=1e-3, branch=2):
+    """samples [n, 5] = (phi, kT, dt_cg/dx, a2, r); returns the table handle."""
+    ss = np.ascontiguousarray(samples, dtype=np.float64)
+    if ss.ndim != 2 or ss.shape[1] != 5 or ss.shape[0] < 1:
+        raise ValueError(f"samples: expected shape (n >= 1, 5), got {ss.shape}")
+    dd = _host(dims, np.int32, 3)
+    h = C.c_void_p()
+    _abi.check(_abi.lib().mdlg_moment_table_create(C.byref(h), ss.ctypes.data_as(C.c_void_p), ss.shape[0],
+                                                   dd.ctypes.data_as(C.c_void_p), float(smooth), int(branch)))
+    return h
+
+
+def mdlg_moment_table_eval(t, x):
+    """x = (phi, kT, dt_cg/dx) -> (a2, lambda, r)."""
+    xx = _host(x, np.float64, 3)
+    a2, lam, r = C.c_double(), C.c_double(), C.c_double()
+    _abi.check(_abi.lib().mdlg_moment_table_eval(t, xx.ctypes.data_as(C.c_void_p), C.byref(a2), C.byref(lam),
+                                                 C.byref(r)))
+    return a2.value, lam.value, r.value
+
+
+def mdlg_moment_table_info(t):
+    """Returns (dims [3], lo [3], hi [3], nodes [P, 2] = (ln a2, r))."""
+    dims = np.zeros(3, np.int32)
+    lo, hi = np.zeros(3), np.zeros(3)
+    _abi.check(_abi.lib().mdlg_moment_table_info(t, dims.ctypes.data_as(C.c_void_p), lo.ctypes.data_as(C.c_void_p),
+                                                 hi.ctypes.data_as(C.c_void_p), None))
+    nodes = np.zeros((int(np.prod(dims)), 2))
+    _abi.check(_abi.lib().mdlg_moment_table_info(t, None, None, None, nodes.ctypes.data_as(C.c_void_p)))
+    return dims, lo, hi, nodes
+
+
+def mdlg_moment_table_destroy(t):
+    _abi.lib().mdlg_moment_table_destroy(t)
+
+
+def mdlg_feq_surrogate_table(h, table, x, tol=1e-3, stream=None):
+    """Returns (g [49] float64, used_fallback bool, max |g_net - g_wsg|, a2, lambda)."""
+    xx = _host(x, np.float64, 6)
+    g = np.zeros(49)
+    fb = C.c_int32(0)
+    err, a2, lam = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+    _abi.check(_abi.lib().mdlg_feq_surrogate_table(h, table, xx.ctypes.data_as(C.c_void_p), float(tol),
+                                                   g.ctypes.data_as(C.c_void_p), C.byref(fb), C.byref(err),
+                                                   C.byref(a2), C.byref(lam), _stream(stream)))
+    return g, bool(fb.value), float(err.value), a2.value, lam.value
+
+
+class MomentTable:
+    """Owns one mdlg_moment_table handle (host memory only)."""
+
+    def __init__(self, samples, dims=(6, 8, 12), smooth=1e-3, branch=2):
+        self.handle = mdlg_moment_table_create(samples, dims, smooth, branch)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mdlg_moment_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, x):
+        return mdlg_moment_table_eval(self.handle, x)
+
+    def info(self):
+        return mdlg_moment_table_info(self.handle)
+
+
 class SurrogateMLP:
     """Owns one mdlg_mlp handle."""
 
@@ -503,6 +577,9 @@ class SurrogateMLP:
 
     def feq(self, x, a2, lam, tol=1e-3):
         return mdlg_feq_surrogate(self.handle, x, a2, lam, tol, self.stream)
+
+    def feq_table(self, x, table: "MomentTable", tol=1e-3):
+        return mdlg_feq_surrogate_table(self.handle, table.handle, x, tol, self.stream)
 
 
 # ------------------------------------------------------ convenience class ---

@@ -13,7 +13,8 @@ LIBPATH = os.path.join(HERE, "libmdlg.so")
 
 MDLG_OK = 0
 STATUS_NAMES = {0: "MDLG_OK", -1: "MDLG_EINVAL", -2: "MDLG_ENOMEM", -3: "MDLG_EHIP", -4: "MDLG_ENONFINITE",
-                -5: "MDLG_ESKIN", -6: "MDLG_ENOTIMPL", -7: "MDLG_ECAPACITY"}
+                -5: "MDLG_ESKIN", -6: "MDLG_ENOTIMPL", -7: "MDLG_ECAPACITY",
+                -8: "MDLG_ERANGE"}
 
 # every symbol declared in include/mdlg.h
 EXPORTS = [
@@ -26,6 +27,8 @@ EXPORTS = [
     "mdlg_neq_mdlg", "mdlg_vacf", "mdlg_lambda_vacf", "mdlg_displacement_hist", "mdlg_pdf_bins", "mdlg_pdf_measured", "mdlg_kl_divergence",
     "mdlg_mlp_create", "mdlg_mlp_params", "mdlg_mlp_forward", "mdlg_mlp_gradient", "mdlg_mlp_train_step",
     "mdlg_feq_surrogate", "mdlg_mlp_destroy",
+    "mdlg_moment_table_create", "mdlg_moment_table_eval", "mdlg_moment_table_info", "mdlg_moment_table_destroy",
+    "mdlg_feq_surrogate_table",
 ]
 
 MLP_NPARAMS = 145969
@@ -145,6 +148,11 @@ def lib() -> C.CDLL:
         "mdlg_mlp_train_step": (i32, [vp, vp, vp, i32, C.c_float, vp, vp]),
         "mdlg_feq_surrogate": (i32, [vp, vp, dbl, dbl, dbl, vp, P(i32), P(dbl), vp]),
         "mdlg_mlp_destroy": (None, [vp]),
+        "mdlg_moment_table_create": (i32, [P(vp), vp, i64, vp, dbl, i32]),
+        "mdlg_moment_table_eval": (i32, [vp, vp, P(dbl), P(dbl), P(dbl)]),
+        "mdlg_moment_table_info": (i32, [vp, vp, vp, vp, vp]),
+        "mdlg_moment_table_destroy": (None, [vp]),
+        "mdlg_feq_surrogate_table": (i32, [vp, vp, vp, dbl, vp, P(i32), P(dbl), P(dbl), P(dbl), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -23,8 +23,21 @@ constexpr int kIn = 6, kHid = 256, kOut = 49;
 constexpr long kW1 = 0, kB1 = 1536, kW2 = 1792, kB2 = 67328, kW3 = 67584, kB3 = 133120, kW4 = 133376, kB4 = 145920;
 constexpr long kParams = 145969;
 constexpr int kMaxSplit = 32;
-// fixed input scaling: phi / 0.4, kT / 20, (dt_cg/dx) * 100, |u| / 0.2, cos, sin
-__constant__ float c_scale[kIn] = {2.5f, 0.05f, 100.0f, 5.0f, 1.0f, 1.0f};
+// Fixed input map of x = (phi, kT, dt_cg/dx, |u|, cos, sin): phi / 0.4,
+// ln kT / ln 20, (ln(dt_cg/dx) + 6) / 1.5, and the drift as the vector
+// 5 |u| (cos, sin) with its length 5 |u|; fp32, every operation rounded once.
+__device__ __forceinline__ float encode_in(const float* __restrict__ xr, int k) {
+#pragma clang fp contract(off)
+    const float inv_ln20 = (float)(1.0 / 2.995732273553991);
+    switch (k) {
+        case 0: return xr[0] * 2.5f;
+        case 1: return logf(fmaxf(xr[1], 1e-30f)) * inv_ln20;
+        case 2: return (logf(fmaxf(xr[2], 1e-30f)) + 6.0f) * (float)(1.0 / 1.5);
+        case 3: return (xr[3] * xr[4]) * 5.0f;
+        case 4: return (xr[3] * xr[5]) * 5.0f;
+        default: return xr[3] * 5.0f;
+    }
+}
 
 // Logistic function and SiLU in fp32, the reciprocal from the hardware
 // estimate (about one ulp); every consumer rounds the result to bf16 (8
@@ -194,7 +207,7 @@ __global__ void k_splitk_reduce(const float* __restrict__ part, int splits, int 
 
 __global__ void k_prep_input(const float* __restrict__ x, int B, bf16* __restrict__ xb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < B * kIn) xb[i] = (bf16)(x[i] * c_scale[i % kIn]);
+    if (i < B * kIn) xb[i] = (bf16)encode_in(x + (long)(i / kIn) * kIn, i % kIn);
 }
 
 __device__ __forceinline__ float wave_max_f(float v) {
@@ -335,7 +348,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int i = tid; i < kFB * 32; i += 256) {
         const int r = i >> 5, k = i & 31;
         float v = 0.f;
-        if (k < kIn && row0 + r < B) v = x[(long)(row0 + r) * kIn + k] * c_scale[k];
+        if (k < kIn && row0 + r < B) v = encode_in(x + (long)(row0 + r) * kIn, k);
         X[r][k] = (bf16)v;
     }
     __syncthreads();
@@ -764,4 +777,16 @@ extern "C" mdlg_status mdlg_feq_surrogate(mdlg_mlp* m, const double* x, double a
     if (used_fallback) *used_fallback = fallback ? 1 : 0;
     if (err) *err = e;
     return MDLG_OK;
+}
+
+extern "C" mdlg_status mdlg_feq_surrogate_table(mdlg_mlp* m, const mdlg_moment_table* table, const double* x,
+                                                double tol, double* g_out, int32_t* used_fallback, double* err,
+                                                double* a2_out, double* lambda_out, void* stream) {
+    if (!m || !table || !x || !g_out) return fail(MDLG_EINVAL, "mdlg_feq_surrogate_table: NULL argument");
+    double a2 = 0.0, lambda = 0.0;
+    mdlg_status s = mdlg_moment_table_eval(table, x, &a2, &lambda, nullptr);
+    if (s != MDLG_OK) return s;
+    if (a2_out) *a2_out = a2;
+    if (lambda_out) *lambda_out = lambda;
+    return mdlg_feq_surrogate(m, x, a2, lambda, tol, g_out, used_fallback, err, stream);
 }

@@ -32,7 +32,7 @@ import numpy as np
 
 import mdlg_inputs as mi
 
-from . import (LJParams, SurrogateMLP, lj_md_destroy, lj_md_get_state, lj_md_init_batch, lj_md_step,
+from . import (LJParams, MomentTable, SurrogateMLP, lj_md_destroy, lj_md_get_state, lj_md_init_batch, lj_md_step,
                mdlg_coarse_grain_series, mdlg_feq_measured, mdlg_feq_wsg, mdlg_lambda_from_moments, mdlg_moments)
 
 DEFAULT_LAGS = (1, 2, 3, 4, 6, 8, 10, 13, 16, 20)
@@ -45,6 +45,7 @@ class SurrogateData:
     overflow: np.ndarray  # [M] fraction beyond |v_a| <= 3
     a2: np.ndarray        # [M] measured a^2 (lattice units)
     lam: np.ndarray       # [M] lambda from the displacement moments
+    r: np.ndarray         # [M] kurtosis ratio mu4 / (3 mu2^2) of the displacements
     rep: np.ndarray       # [M] replica id (for splits without leakage)
     u: np.ndarray         # [M, 2] drift, cells per coarse step
     samples: np.ndarray   # [M] particle events behind each g
@@ -54,7 +55,7 @@ class SurrogateData:
         return self.X.shape[0]
 
     def subset(self, idx):
-        return SurrogateData(self.X[idx], self.G[idx], self.overflow[idx], self.a2[idx], self.lam[idx],
+        return SurrogateData(self.X[idx], self.G[idx], self.overflow[idx], self.a2[idx], self.lam[idx], self.r[idx],
                              self.rep[idx], self.u[idx], self.samples[idx], dict(self.timing))
 
 
@@ -82,7 +83,7 @@ def generate(n_groups=4, reps_per_group=80, n=65536, n_snap=401, stride=10, equi
     """Run the sample design above on the GPU; returns the measured equilibria."""
     import torch
     lags = tuple(int(l) for l in lags)
-    out = {k: [] for k in ("X", "G", "overflow", "a2", "lam", "rep", "u", "samples")}
+    out = {k: [] for k in ("X", "G", "overflow", "a2", "lam", "r", "rep", "u", "samples")}
     t_md = t_cg = 0.0
     for g in range(n_groups):
         specs = mi.surrogate_sweep(reps_per_group, seed=seed + g, n=n)
@@ -132,7 +133,7 @@ def generate(n_groups=4, reps_per_group=80, n=65536, n_snap=401, stride=10, equi
             for si, l in enumerate(lags):
                 pairs = n_snap - l
                 mu2, mu4, a2 = mdlg_moments(moments[r, si], dx)
-                lam, _ = mdlg_lambda_from_moments(mu2, mu4, 2)
+                lam, kr = mdlg_lambda_from_moments(mu2, mu4, 2)
                 for t in range(n_u):
                     um = float(np.hypot(*u[t]))
                     c, sn = (u[t] / um) if um > 0 else (1.0, 0.0)
@@ -142,13 +143,14 @@ def generate(n_groups=4, reps_per_group=80, n=65536, n_snap=401, stride=10, equi
                     out["overflow"].append(ovf)
                     out["a2"].append(a2)
                     out["lam"].append(lam)
+                    out["r"].append(kr)
                     out["rep"].append(g * reps_per_group + r)
                     out["u"].append(u[t])
                     out["samples"].append(s.n * pairs)
         if log:
             log(f"surrogate data: group {g + 1}/{n_groups} ({len(specs)} replicas x {n} particles): "
                 f"MD {t1 - t0:.2f} s, coarse-graining {t2 - t1:.3f} s")
-    d = SurrogateData(*(np.asarray(out[k], dtype=np.float64) for k in ("X", "G", "overflow", "a2", "lam")),
+    d = SurrogateData(*(np.asarray(out[k], dtype=np.float64) for k in ("X", "G", "overflow", "a2", "lam", "r")),
                       np.asarray(out["rep"], dtype=np.int64), np.asarray(out["u"], dtype=np.float64),
                       np.asarray(out["samples"], dtype=np.int64))
     d.timing = {"md_s": t_md, "cg_s": t_cg,
@@ -217,26 +219,48 @@ def predict(net: SurrogateMLP, X):
     return np.concatenate(out)
 
 
-def wsg_table(data: SurrogateData, idx):
-    """Poisson-WSG equilibrium of each sample from its measured a^2 and lambda."""
-    return np.stack([mdlg_feq_wsg(data.a2[i], data.lam[i], data.u[i]) for i in idx])
+def moment_table(data: SurrogateData, idx, dims=(6, 8, 12), smooth=1e-3):
+    """The library's moment table fitted to the measured (a^2, r) of the given
+    samples (one row per replica and coarse-graining time), for the guard at
+    points where no trajectory exists."""
+    _, first = np.unique(np.stack([data.rep[idx], data.X[idx, 2]], axis=1), axis=0, return_index=True)
+    sel = np.asarray(idx)[np.sort(first)]
+    rows = np.stack([data.X[sel, 0], data.X[sel, 1], data.X[sel, 2], data.a2[sel], data.r[sel]], axis=1)
+    return MomentTable(rows, dims=dims, smooth=smooth, branch=2)
 
 
-def evaluate(net: SurrogateMLP, data: SurrogateData, idx, tol=1e-3, with_guard=False):
+def wsg_table(data: SurrogateData, idx, table: MomentTable | None = None):
+    """Poisson-WSG equilibrium of each sample: from its measured a^2 and lambda,
+    or, given a table, from the table's a^2 and lambda at (phi, kT, dt_cg/dx)."""
+    if table is None:
+        return np.stack([mdlg_feq_wsg(data.a2[i], data.lam[i], data.u[i]) for i in idx])
+    out = []
+    for i in idx:
+        a2, lam, _ = table(data.X[i, :3])
+        out.append(mdlg_feq_wsg(a2, lam, data.u[i]))
+    return np.stack(out)
+
+
+def evaluate(net: SurrogateMLP, data: SurrogateData, idx, tol=1e-3, with_guard=False, table=None):
     """Errors of the network against the measured g (max over the 49 values per
-    sample); with_guard adds the WSG comparison and the fallback rate at tol."""
+    sample); with_guard adds the WSG comparison and the fallback rate at tol,
+    with the measured moments of each sample and, given a moment table, with
+    the table's (the guard that needs no trajectory)."""
     g = predict(net, data.X[idx])
     err = np.abs(g - data.G[idx]).max(axis=1)
     res = {"max_err": float(err.max()), "mean_err": float(err.mean()), "p99_err": float(np.quantile(err, 0.99)),
            "frac_below_tol": float(np.mean(err <= tol)), "n": int(len(idx))}
     if with_guard:
-        w = wsg_table(data, idx)
-        dev_wsg = np.abs(g - w).max(axis=1)
-        fallback = dev_wsg > tol
-        final = np.where(fallback[:, None], w, g)
-        e_final = np.abs(final - data.G[idx]).max(axis=1)
-        e_wsg = np.abs(w - data.G[idx]).max(axis=1)
-        res.update({"fallback_rate": float(fallback.mean()), "guarded_max_err": float(e_final.max()),
-                    "guarded_mean_err": float(e_final.mean()), "wsg_max_err": float(e_wsg.max()),
-                    "wsg_mean_err": float(e_wsg.mean())})
+        for key, tab in (("", None), ("table_", table)):
+            if key and tab is None:
+                continue
+            w = wsg_table(data, idx, tab)
+            dev_wsg = np.abs(g - w).max(axis=1)
+            fallback = dev_wsg > tol
+            final = np.where(fallback[:, None], w, g)
+            e_final = np.abs(final - data.G[idx]).max(axis=1)
+            e_wsg = np.abs(w - data.G[idx]).max(axis=1)
+            res.update({key + "fallback_rate": float(fallback.mean()), key + "guarded_max_err": float(e_final.max()),
+                        key + "guarded_mean_err": float(e_final.mean()), key + "wsg_max_err": float(e_wsg.max()),
+                        key + "wsg_mean_err": float(e_wsg.mean())})
     return res

@@ -2,7 +2,7 @@
 accumulation) with its FP64 reference:
 
 * forward: within 2e-3 relative of the reference evaluated with the same
-  bf16 roundings (weights, scaled inputs, hidden activations), and within
+  bf16 roundings (weights, encoded inputs, hidden activations), and within
   the bf16 error budget (3e-2 relative) of the exact FP64 network;
 * gradient: per parameter block cosine >= 0.999 and relative L2 <= 3e-2
   against the exact FP64 backpropagation;
@@ -40,7 +40,7 @@ def params(seed=0):
 def forward_bf16(theta, X):
     """The reference forward pass with the kernel's bf16 roundings applied."""
     W1, b1, W2, b2, W3, b3, W4, b4 = om.unpack(theta)
-    h = om.to_bf16(np.asarray(X, np.float32).astype(np.float64) * om.SCALE.astype(np.float32))
+    h = om.to_bf16(om.encode(np.asarray(X, np.float32), dtype=np.float32).astype(np.float64))
     for W, b in ((W1, b1), (W2, b2), (W3, b3)):
         z = h @ om.to_bf16(W) + b
         h = om.to_bf16(om.silu(z))
@@ -128,7 +128,7 @@ def test_training_lowers_the_loss():
     X = inputs(9, B)
     # targets that depend smoothly on the inputs, so that the batch can be fitted
     M = np.random.default_rng(4).normal(size=(6, 49))
-    R = om.softmax(2.0 * (X * om.SCALE) @ M)
+    R = om.softmax(2.0 * om.encode(X) @ M)
     net = make(theta, B)
     x, r = _t(X), _t(R)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")

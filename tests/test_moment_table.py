@@ -1,0 +1,121 @@
+"""The moment table behind the surrogate's guard (host code, no GPU).
+
+Pins: a multilinear function of (phi, ln kT, ln(dt_cg/dx)) has zero second
+differences along every axis, so the penalised least-squares fit reproduces
+it exactly, at nodes and between them; the ballistic law a^2 = kT (dt/dx)^2
+is such a function (ln a^2 = ln kT + 2 ln(dt/dx)); lambda follows r through
+the closed-form root of Eq.(lambda_eq); a smooth non-multilinear field
+converges at second order in the node spacing.
+"""
+import numpy as np
+import pytest
+
+import paper_2101_01160_amd as m
+from paper_2101_01160_amd._abi import MDLGError
+
+
+def _box(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    phi = rng.uniform(0.05, 0.4, n)
+    kT = np.exp(rng.uniform(0.0, np.log(20.0), n))
+    tau = np.exp(rng.uniform(np.log(1e-3), np.log(2e-2), n))
+    return phi, kT, tau
+
+
+def _multilinear(c, phi, lk, lt):
+    return (c[0] + c[1] * phi + c[2] * lk + c[3] * lt + c[4] * phi * lk + c[5] * phi * lt + c[6] * lk * lt
+            + c[7] * phi * lk * lt)
+
+
+def _samples(fa, fr, n=3000, seed=0):
+    phi, kT, tau = _box(n, seed)
+    return np.stack([phi, kT, tau, fa(phi, kT, tau), fr(phi, kT, tau)], axis=1)
+
+
+def _inner_points(t, n, seed):
+    """Points inside the table's bounding box, away from its edges by 1%."""
+    _, lo, hi, _ = t.info()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = rng.uniform(0.01, 0.99, (n, 3))
+    c = lo + f * (hi - lo)
+    return np.stack([c[:, 0], np.exp(c[:, 1]), np.exp(c[:, 2])], axis=1)
+
+
+def test_multilinear_fields_are_reproduced_exactly():
+    ca = np.array([-1.0, 0.7, 0.9, 1.8, -0.2, 0.15, 0.05, -0.03])
+    cr = np.array([1.02, 0.1, -0.004, 0.006, 0.01, -0.02, 0.0007, 0.001])
+    fa = lambda p, k, t: np.exp(_multilinear(ca, p, np.log(k), np.log(t)))
+    fr = lambda p, k, t: _multilinear(cr, p, np.log(k), np.log(t))
+    t = m.MomentTable(_samples(fa, fr), dims=(4, 5, 6), smooth=1e-2)
+    for x in _inner_points(t, 200, 1):
+        a2, lam, r = t(x)
+        assert np.log(a2) == pytest.approx(np.log(fa(*x)), abs=1e-9)
+        assert r == pytest.approx(fr(*x), abs=1e-10)
+
+
+def test_ballistic_law_and_lambda_root():
+    # a^2 = kT (dt/dx)^2 and a constant kurtosis ratio r = 1.05
+    fa = lambda p, k, t: k * t * t
+    fr = lambda p, k, t: np.full_like(p, 1.05)
+    t = m.MomentTable(_samples(fa, fr, n=500), dims=(2, 3, 3), smooth=1e-3, branch=2)
+    lam_ref, _ = m.mdlg_lambda_from_moments(1.0, 3.0 * 1.05, 2)
+    # Eq.(lambda_eq) with r = 1.05: mu4 / (3 mu2^2) = (l^2 + 3 l + 1) / (l + 1)^2
+    assert (lam_ref ** 2 + 3 * lam_ref + 1) / (lam_ref + 1) ** 2 == pytest.approx(1.05, rel=1e-12)
+    for x in _inner_points(t, 50, 2):
+        a2, lam, r = t(x)
+        assert a2 == pytest.approx(x[1] * x[2] ** 2, rel=1e-9)
+        assert lam == pytest.approx(lam_ref, rel=1e-9)
+    t1 = m.MomentTable(_samples(fa, fr, n=500), dims=(2, 3, 3), smooth=1e-3, branch=1)
+    assert t1(_inner_points(t1, 1, 3)[0])[1] == pytest.approx(1.0 / lam_ref, rel=1e-9)
+
+
+def test_smooth_field_converges_at_second_order():
+    fa = lambda p, k, t: np.exp(np.sin(6.0 * p) + 0.3 * np.log(k) ** 2 / 9.0 + 1.5 * np.log(t))
+    fr = lambda p, k, t: 1.0 + 0.05 * np.cos(4.0 * p) * np.exp(-k / 10.0)
+    s = _samples(fa, fr, n=20000, seed=4)
+    errs = []
+    for d in (3, 5, 9):
+        t = m.MomentTable(s, dims=(d, d, d), smooth=1e-4)
+        xs = _inner_points(t, 300, 5)
+        e = max(abs(np.log(t(x)[0]) - np.log(fa(*x))) for x in xs)
+        errs.append(e)
+    # node spacing halves from 3 to 5 and again to 9 nodes
+    assert errs[1] < errs[0] / 2.5 and errs[2] < errs[1] / 2.5, errs
+
+
+def test_bounds_range_and_errors():
+    fa = lambda p, k, t: k * t * t
+    fr = lambda p, k, t: np.full_like(p, 1.0)
+    s = _samples(fa, fr, n=400, seed=6)
+    t = m.MomentTable(s, dims=(3, 3, 3))
+    dims, lo, hi, nodes = t.info()
+    assert list(dims) == [3, 3, 3] and nodes.shape == (27, 2)
+    assert lo == pytest.approx([s[:, 0].min(), np.log(s[:, 1]).min(), np.log(s[:, 2]).min()], abs=0)
+    assert hi == pytest.approx([s[:, 0].max(), np.log(s[:, 1]).max(), np.log(s[:, 2]).max()], abs=0)
+    # r = 1 is the Gaussian: lambda = 0 on either branch
+    assert t(s[0, :3])[1] == 0.0
+    # a corner sample is inside; a point beyond any edge is out of range
+    with pytest.raises(MDLGError, match="MDLG_ERANGE"):
+        t((hi[0] + 0.01, s[0, 1], s[0, 2]))
+    with pytest.raises(MDLGError, match="MDLG_ERANGE"):
+        t((s[0, 0], np.exp(lo[1]) * 0.9, s[0, 2]))
+    with pytest.raises(MDLGError, match="MDLG_EINVAL"):
+        t((s[0, 0], -1.0, s[0, 2]))
+    # an axis without spread needs one node
+    flat = s.copy()
+    flat[:, 0] = 0.2
+    with pytest.raises(MDLGError, match="no spread"):
+        m.MomentTable(flat, dims=(2, 3, 3))
+    tf = m.MomentTable(flat, dims=(1, 3, 3))
+    assert tf((0.2, s[1, 1], s[1, 2]))[0] == pytest.approx(s[1, 1] * s[1, 2] ** 2, rel=1e-9)
+    # no penalty and nodes that no sample reaches: singular
+    few = s[:3]
+    with pytest.raises(MDLGError, match="singular"):
+        m.MomentTable(few, dims=(3, 3, 3), smooth=0.0)
+    for bad in ((0, 3, 3), (65, 1, 1), (16, 16, 16)):
+        with pytest.raises(MDLGError, match="MDLG_EINVAL"):
+            m.MomentTable(s, dims=bad)
+    neg = s.copy()
+    neg[5, 3] = -1.0
+    with pytest.raises(MDLGError, match="sample 5"):
+        m.MomentTable(neg, dims=(3, 3, 3))
