@@ -63,13 +63,15 @@ def parse():
     ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
     ap.add_argument("--precision-steps", type=int, default=10000, help="precision: MD steps per run")
     ap.add_argument("--replicas", type=int, default=256)
-    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
-    ap.add_argument("--train-batch", type=int, default=4096, help="surrogate: minibatch")
+    ap.add_argument("--train-steps", type=int, default=100000, help="surrogate: Adam steps")
+    ap.add_argument("--train-batch", type=int, default=2048, help="surrogate: minibatch")
     ap.add_argument("--groups", type=int, default=4, help="surrogate: replica groups (80 replicas each)")
     ap.add_argument("--paper-replicas", type=int, default=4, help="paper: independent systems of 99,856 particles")
     ap.add_argument("--events", type=int, default=20, help="paper: coarse-graining events per Table 1 row (2000 in the paper)")
     ap.add_argument("--equil", type=int, default=1000000, help="paper: MD steps discarded before the sweep")
     ap.add_argument("--rows", default="", help="paper: comma-separated Table 1 rows (0-11); default all")
+    ap.add_argument("--paper-rc", type=float, default=2.5,
+                    help="paper: LJ cutoff in sigma (energy-shifted); 2^(1/6) gives the purely repulsive WCA potential")
     ap.add_argument("--stop-at", type=int, default=0, help="paper: stop the sweep before this MD step (0: run to the end)")
     ap.add_argument("--checkpoint", default="", help="paper: write state and accumulators here when stopping early")
     ap.add_argument("--resume", default="", help="paper: continue the sweep from a checkpoint")
@@ -83,7 +85,7 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step3_nlist_1M_phi0.0784.traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fused3_1M_phi0.0784.traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01160_amd", "csrc", "md.hip")
 
 
@@ -601,15 +603,19 @@ def bench_surrogate(args):
     t_gen = time.perf_counter() - t0
     tr, va, te = S.split_by_replica(data)
     net, hist = S.train(data, tr, steps=args.train_steps, batch=args.train_batch, val_idx=va,
-                        val_every=max(1, args.train_steps // 8), log=log)
-    res = S.evaluate(net, data, te, with_guard=True)
+                        val_every=max(1, args.train_steps // 8), log=log, average_tail=0.3)
+    table = S.moment_table(data, tr, box=S.parameter_box(data))
+    res = S.evaluate(net, data, te, with_guard=True, table=table)
     log(f"held-out: {res}")
-    # the guard through the C entry point on a sample of held-out points
+    # the guard without a trajectory through the C entry point on a sample of
+    # held-out points: same rule as the batched evaluation
     sample = te[:: max(1, len(te) // 64)]
     agree = 0
+    t_guard = time.perf_counter()
     for i in sample:
-        g, fb, err = net.feq(data.X[i], data.a2[i], data.lam[i], tol=1e-3)
+        g, fb, err, _, _ = net.feq_table(data.X[i], table, tol=1e-3)
         agree += int(fb == (err > 1e-3))
+    us_guard = (time.perf_counter() - t_guard) / len(sample) * 1e6
     # inference throughput: one launch sequence for a large batch, HIP events
     B = 65536
     big = m.SurrogateMLP(net.params(), B)
@@ -630,8 +636,7 @@ def bench_surrogate(args):
     tflops = MLP_FLOP_PER_SAMPLE * B / (ms_inf * 1e-3) / 1e12
     # training step time (GPU work plus launch overhead), fixed batch
     x4 = torch.from_numpy(data.X[tr[:args.train_batch]].astype(np.float32)).cuda()
-    r4 = torch.from_numpy((data.G[tr[:args.train_batch]] /
-                           data.G[tr[:args.train_batch]].sum(axis=1, keepdims=True)).astype(np.float32)).cuda()
+    r4 = torch.from_numpy(data.G[tr[:args.train_batch]].astype(np.float32)).cuda()
     lbuf = torch.zeros(1, dtype=torch.float32, device="cuda")
     probe = m.SurrogateMLP(net.params(), args.train_batch)
     for _ in range(3):
@@ -659,7 +664,7 @@ def bench_surrogate(args):
                    "train_batch": args.train_batch},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tflops / 2500.0, "traffic": None},
-        "heldout": res, "guard_agreement": agree / len(sample),
+        "heldout": res, "guard_agreement": agree / len(sample), "guard_call_us": us_guard,
         "timing": {"generate_s": t_gen, "md_s": data.timing["md_s"], "coarse_grain_s": data.timing["cg_s"],
                    "train_s": hist["train_s"], "train_step_us": us_train, "inference_us_per_batch": ms_inf * 1e3},
         "gain": {"md_particle_steps_per_feq": steps_per_sample, "md_seconds_per_feq": sec_md_per_sample,
@@ -831,7 +836,7 @@ def bench_paper(args):
             rng = np.random.Generator(np.random.PCG64(args.seed + r))
             pos.append(mi.jittered_grid(N, L, rng))
             vel.append(mi.maxwell_velocities(N, kT, rng))
-        params = [m.lj_params(N, L, force_bits=args.force_bits) for _ in range(R)]
+        params = [m.lj_params(N, L, rc=args.paper_rc, force_bits=args.force_bits) for _ in range(R)]
         sysm = m.LJSystem(torch.from_numpy(np.concatenate(pos)).to(dev),
                           torch.from_numpy(np.concatenate(vel)).to(dev), params=params)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -986,7 +991,7 @@ def bench_paper(args):
         "dtype": "f64" if args.force_bits == 64 else "f64 state, f32 pair forces",
         "data": "synthetic (jittered-grid positions, Maxwellian velocities, seeds %d..%d)" % (args.seed,
                                                                                          args.seed + R - 1),
-        "config": {"workload": f"{R} x 2D LJ gas N={N}, L={L}, phi={phi:.6f}, kT={kT}, dt=1e-4; "
+        "config": {"workload": f"{R} x 2D LJ gas N={N}, L={L}, phi={phi:.6f}, kT={kT}, rc={args.paper_rc:g}, dt=1e-4; "
                                f"{equil_info['md_steps']} equilibration steps; Table 1 rows {rows}, {E} coarse "
                                f"steps each from one trajectory", "replicas": R, "events_per_row": E,
                    "equil_steps": equil_info["md_steps"]},

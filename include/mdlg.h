@@ -529,12 +529,16 @@ typedef struct mdlg_moment_table mdlg_moment_table;
 
 /* samples host [n][5] = (phi, kT, dt_cg/dx, a2, r) with kT, dt_cg/dx, a2 > 0;
  * dims host [3], each in [1, 64], product <= 2048 (an axis whose samples do
- * not spread needs dims 1); smooth >= 0 (0 only when samples reach every
- * node); branch 1 or 2.  Errors: EINVAL (arguments, or a singular fit). */
+ * not spread needs dims 1); lo, hi host [3] = (phi, kT, dt_cg/dx): the box
+ * the grid spans (both NULL: the samples' bounding box; given, it must hold
+ * every sample, and the penalty extends the fit linearly to its edges);
+ * smooth >= 0 (0 only when samples reach every node); branch 1 or 2.
+ * Errors: EINVAL (arguments, or a singular fit). */
 mdlg_status mdlg_moment_table_create(mdlg_moment_table** out, const double* samples, int64_t n,
-                                     const int32_t* dims, double smooth, int32_t branch);
+                                     const int32_t* dims, const double* lo, const double* hi,
+                                     double smooth, int32_t branch);
 /* x host [3] = (phi, kT, dt_cg/dx) -> a2, lambda and r (each may be NULL).
- * ERANGE when x lies outside the fitted range (the samples' bounding box). */
+ * ERANGE when x lies outside the grid's box. */
 mdlg_status mdlg_moment_table_eval(const mdlg_moment_table* table, const double* x, double* a2,
                                    double* lambda, double* r);
 /* The grid: dims [3], coordinate bounds lo/hi [3] (phi, ln kT, ln(dt_cg/dx))

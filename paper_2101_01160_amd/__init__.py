@@ -472,15 +472,22 @@ def mdlg_mlp_destroy(h):
     _abi.lib().mdlg_mlp_destroy(h)
 
 
-def mdlg_moment_table_create(samples, dims=(6, 8, 12), smooth=1e-3, branch=2):
-    """samples [n, 5] = (phi, kT, dt_cg/dx, a2, r); returns the table handle."""
+def mdlg_moment_table_create(samples, dims=(6, 8, 12), smooth=1e-3, branch=2, lo=None, hi=None):
+    """samples [n, 5] = (phi, kT, dt_cg/dx, a2, r); lo, hi (phi, kT, dt_cg/dx):
+    the grid's box (default: the samples' bounding box); returns the handle."""
     ss = np.ascontiguousarray(samples, dtype=np.float64)
     if ss.ndim != 2 or ss.shape[1] != 5 or ss.shape[0] < 1:
         raise ValueError(f"samples: expected shape (n >= 1, 5), got {ss.shape}")
     dd = _host(dims, np.int32, 3)
+    if (lo is None) != (hi is None):
+        raise ValueError("give both lo and hi, or neither")
+    ll = None if lo is None else _host(lo, np.float64, 3)
+    hh = None if hi is None else _host(hi, np.float64, 3)
     h = C.c_void_p()
-    _abi.check(_abi.lib().mdlg_moment_table_create(C.byref(h), ss.ctypes.data_as(C.c_void_p), ss.shape[0],
-                                                   dd.ctypes.data_as(C.c_void_p), float(smooth), int(branch)))
+    _abi.check(_abi.lib().mdlg_moment_table_create(
+        C.byref(h), ss.ctypes.data_as(C.c_void_p), ss.shape[0], dd.ctypes.data_as(C.c_void_p),
+        None if ll is None else ll.ctypes.data_as(C.c_void_p), None if hh is None else hh.ctypes.data_as(C.c_void_p),
+        float(smooth), int(branch)))
     return h
 
 
@@ -523,8 +530,8 @@ def mdlg_feq_surrogate_table(h, table, x, tol=1e-3, stream=None):
 class MomentTable:
     """Owns one mdlg_moment_table handle (host memory only)."""
 
-    def __init__(self, samples, dims=(6, 8, 12), smooth=1e-3, branch=2):
-        self.handle = mdlg_moment_table_create(samples, dims, smooth, branch)
+    def __init__(self, samples, dims=(6, 8, 12), smooth=1e-3, branch=2, lo=None, hi=None):
+        self.handle = mdlg_moment_table_create(samples, dims, smooth, branch, lo, hi)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -148,7 +148,7 @@ def lib() -> C.CDLL:
         "mdlg_mlp_train_step": (i32, [vp, vp, vp, i32, C.c_float, vp, vp]),
         "mdlg_feq_surrogate": (i32, [vp, vp, dbl, dbl, dbl, vp, P(i32), P(dbl), vp]),
         "mdlg_mlp_destroy": (None, [vp]),
-        "mdlg_moment_table_create": (i32, [P(vp), vp, i64, vp, dbl, i32]),
+        "mdlg_moment_table_create": (i32, [P(vp), vp, i64, vp, vp, vp, dbl, i32]),
         "mdlg_moment_table_eval": (i32, [vp, vp, P(dbl), P(dbl), P(dbl)]),
         "mdlg_moment_table_info": (i32, [vp, vp, vp, vp, vp]),
         "mdlg_moment_table_destroy": (None, [vp]),

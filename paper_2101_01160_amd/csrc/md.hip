@@ -1032,6 +1032,9 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
     const unsigned char* __restrict__ tc = a.tcnt + (long long)t * kPairCap;
     const unsigned int SL = (unsigned int)kPairCap;
     const int qf = threadIdx.x;
+    // the block's histogram starts from zero (ordered before its first use by
+    // the staging barrier; cleared first so that no address stays live)
+    if (CG && qf < MDLG_NCOUNTS) hist[qf] = 0;
     const int s_first = list[qf];
     const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
     const int nn_first = tc[qf];
@@ -1072,7 +1075,6 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
     if (qf < nvel) vs[qf] = v0;
     if (h1) xa[qf + BS] = p1;
     if (qf + BS < nvel) vs[qf + BS] = v1;
-    if (CG && qf < MDLG_NCOUNTS) hist[qf] = 0;
     __syncthreads();
     // an intermediate step: particles [0, count) from src into dst (LDS); the
     // image changes of owned particles are kept (set on the first step, added

@@ -10,8 +10,9 @@
 // with tensor-product hat functions B_p (multilinear interpolation between
 // the nodes) and the second differences taken along each axis in node
 // units, w = smooth * n / P.  The penalty fixes nodes that no sample
-// touches and vanishes for every multilinear function, which the fit
-// therefore reproduces exactly.  ln a^2 is close to linear in the two
+// touches (extending the fit linearly beyond the samples, up to the edges of
+// a caller-given box) and vanishes for every multilinear function, which the
+// fit therefore reproduces exactly.  ln a^2 is close to linear in the two
 // logarithms in the ballistic limit (a^2 = kT (dt_cg/dx)^2 there).
 #include <cmath>
 #include <string>
@@ -114,7 +115,8 @@ bool cholesky_solve(std::vector<double>& A, int P, std::vector<double>& b, int n
 extern "C" void mdlg_moment_table_destroy(mdlg_moment_table* t) { delete t; }
 
 extern "C" mdlg_status mdlg_moment_table_create(mdlg_moment_table** out, const double* samples, int64_t n,
-                                                const int32_t* dims, double smooth, int32_t branch) {
+                                                const int32_t* dims, const double* lo, const double* hi,
+                                                double smooth, int32_t branch) {
     if (!out || !samples || !dims) return mdlg::fail(MDLG_EINVAL, "mdlg_moment_table_create: NULL argument");
     *out = nullptr;
     if (n < 1) return mdlg::fail(MDLG_EINVAL, "mdlg_moment_table_create: need at least one sample");
@@ -150,6 +152,27 @@ extern "C" mdlg_status mdlg_moment_table_create(mdlg_moment_table** out, const d
         }
         ys[(size_t)s * 2] = std::log(row[3]);
         ys[(size_t)s * 2 + 1] = row[4];
+    }
+    if ((lo == nullptr) != (hi == nullptr)) {
+        delete t;
+        return mdlg::fail(MDLG_EINVAL, "mdlg_moment_table_create: give both lo and hi, or neither");
+    }
+    if (lo) {
+        // a caller-given box (the design's parameter range): it must hold every sample
+        double clo[3], chi[3];
+        if (!coords(lo, clo) || !coords(hi, chi)) {
+            delete t;
+            return mdlg::fail(MDLG_EINVAL, "mdlg_moment_table_create: lo and hi need finite phi, kT > 0, dt_cg/dx > 0");
+        }
+        for (int a = 0; a < 3; ++a) {
+            const double eps = 1e-9 * std::fmax(chi[a] - clo[a], 1e-300);
+            if (!(chi[a] >= clo[a]) || t->lo[a] < clo[a] - eps || t->hi[a] > chi[a] + eps) {
+                delete t;
+                return mdlg::fail(MDLG_EINVAL, "mdlg_moment_table_create: the box lo..hi must hold every sample");
+            }
+            t->lo[a] = clo[a];
+            t->hi[a] = chi[a];
+        }
     }
     for (int a = 0; a < 3; ++a)
         if (dims[a] > 1 && !(t->hi[a] > t->lo[a])) {

@@ -171,9 +171,12 @@ def split_by_replica(data: SurrogateData, seed=0, frac=(0.8, 0.1, 0.1)):
 
 
 def train(data: SurrogateData, idx, steps=4000, batch=4096, lr=2e-3, lr_final=2e-5, init_seed=0, seed=0,
-          val_idx=None, val_every=500, log=None):
+          val_idx=None, val_every=500, log=None, average_tail=0.0, average_every=100):
     """Adam on minibatches drawn without replacement per epoch; cosine learning rate.
-    Returns (network, history dict)."""
+    With average_tail > 0 the returned network holds the mean of the
+    parameters taken every `average_every` steps over that last fraction of
+    the steps (weight averaging: it removes most of the minibatch noise the
+    final iterate carries).  Returns (network, history dict)."""
     import torch
     net = SurrogateMLP(mi.mlp_init(init_seed).astype(np.float32), max(batch, 1))
     X = torch.from_numpy(data.X[idx].astype(np.float32)).cuda()
@@ -186,6 +189,8 @@ def train(data: SurrogateData, idx, steps=4000, batch=4096, lr=2e-3, lr_final=2e
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     hist = {"step": [], "loss": [], "val_max_err": []}
     perm, pos = torch.from_numpy(rng.permutation(m)).cuda(), 0
+    avg_from = steps - int(round(average_tail * steps)) if average_tail > 0 else steps
+    avg_sum, avg_n = None, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -197,6 +202,10 @@ def train(data: SurrogateData, idx, steps=4000, batch=4096, lr=2e-3, lr_final=2e
         rb = R.index_select(0, sel)
         lr_k = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * k / max(1, steps - 1)))
         net.train_step(xb, rb, lr_k, loss)
+        if k >= avg_from and (k + 1 - avg_from) % average_every == 0:
+            p = net.params().astype(np.float64)
+            avg_sum = p if avg_sum is None else avg_sum + p
+            avg_n += 1
         if (k + 1) % val_every == 0 or k + 1 == steps:
             hist["step"].append(k + 1)
             hist["loss"].append(float(loss.cpu()[0]))
@@ -205,6 +214,9 @@ def train(data: SurrogateData, idx, steps=4000, batch=4096, lr=2e-3, lr_final=2e
             if log:
                 v = f" val max|dg| {hist['val_max_err'][-1]:.2e}" if val_idx is not None else ""
                 log(f"surrogate train: step {k + 1}/{steps} loss {hist['loss'][-1]:.3e}{v}")
+    if avg_n:
+        net = SurrogateMLP((avg_sum / avg_n).astype(np.float32), max(batch, 1))
+        hist["averaged"] = avg_n
     torch.cuda.synchronize()
     hist["train_s"] = time.perf_counter() - t0
     return net, hist
@@ -219,14 +231,22 @@ def predict(net: SurrogateMLP, X):
     return np.concatenate(out)
 
 
-def moment_table(data: SurrogateData, idx, dims=(6, 8, 12), smooth=1e-3):
+def moment_table(data: SurrogateData, idx, dims=(6, 8, 12), smooth=1e-3, box=None):
     """The library's moment table fitted to the measured (a^2, r) of the given
     samples (one row per replica and coarse-graining time), for the guard at
-    points where no trajectory exists."""
+    points where no trajectory exists.  box = (lo, hi) over (phi, kT,
+    dt_cg/dx), the parameter range to cover (default: the samples' own)."""
     _, first = np.unique(np.stack([data.rep[idx], data.X[idx, 2]], axis=1), axis=0, return_index=True)
     sel = np.asarray(idx)[np.sort(first)]
     rows = np.stack([data.X[sel, 0], data.X[sel, 1], data.X[sel, 2], data.a2[sel], data.r[sel]], axis=1)
-    return MomentTable(rows, dims=dims, smooth=smooth, branch=2)
+    lo, hi = (None, None) if box is None else box
+    return MomentTable(rows, dims=dims, smooth=smooth, branch=2, lo=lo, hi=hi)
+
+
+def parameter_box(data: SurrogateData):
+    """The design's parameter range over (phi, kT, dt_cg/dx) as its inputs
+    span it (no measured value enters)."""
+    return data.X[:, :3].min(axis=0), data.X[:, :3].max(axis=0)
 
 
 def wsg_table(data: SurrogateData, idx, table: MomentTable | None = None):

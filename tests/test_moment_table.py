@@ -119,3 +119,24 @@ def test_bounds_range_and_errors():
     neg[5, 3] = -1.0
     with pytest.raises(MDLGError, match="sample 5"):
         m.MomentTable(neg, dims=(3, 3, 3))
+
+
+def test_given_box_extends_the_fit_linearly():
+    # samples cover only part of the box; a field linear in the coordinates is
+    # reproduced beyond them (the second-difference penalty extrapolates linearly)
+    fa = lambda p, k, t: np.exp(-2.0 + 0.5 * p + np.log(k) + 2.0 * np.log(t))
+    fr = lambda p, k, t: 1.0 + 0.01 * p + 0.002 * np.log(k)
+    s = _samples(fa, fr, n=2000, seed=7)
+    keep = (s[:, 0] < 0.3) & (s[:, 1] < 10.0)
+    lo, hi = (0.05, 1.0, 1e-3), (0.4, 20.0, 2e-2)
+    t = m.MomentTable(s[keep], dims=(5, 5, 5), smooth=1e-2, lo=lo, hi=hi)
+    dims, tlo, thi, _ = t.info()
+    assert tlo == pytest.approx([0.05, 0.0, np.log(1e-3)], abs=1e-15)
+    for x in ((0.39, 19.0, 1.5e-3), (0.35, 15.0, 1.9e-2), (0.05, 1.0, 1e-3)):
+        a2, _, r = t(x)
+        assert np.log(a2) == pytest.approx(np.log(fa(*x)), abs=1e-8)
+        assert r == pytest.approx(fr(*x), abs=1e-10)
+    with pytest.raises(MDLGError, match="hold every sample"):
+        m.MomentTable(s, dims=(3, 3, 3), lo=(0.1, 1.0, 1e-3), hi=hi)
+    with pytest.raises(ValueError):
+        m.MomentTable(s, dims=(3, 3, 3), lo=lo)
