@@ -96,6 +96,11 @@ struct StepArgs {
     const int* __restrict__ ptile_rep;          // [tiles] replica
     int* __restrict__ cell_acc;
     const long long* __restrict__ event_k;
+    // the previous event's finish, done by blocks [0, fin_n) of a later launch
+    // (0: none; see cg_finish_one)
+    int fin_n;
+    double* __restrict__ moments;
+    long long* __restrict__ event_kw;
     // cell binning on the last launch before a rebuild (counting sort input)
     int* __restrict__ cnt;
     int* __restrict__ key;
@@ -196,12 +201,29 @@ __device__ __forceinline__ void pair_forces(const double2* __restrict__ pin, con
 // Lattice velocity index (D2Q49, 49 = overflow) and destination cell of one
 // particle between its snapshot sp (coarse step k-1) and position p (step k).
 __device__ __forceinline__ int cg_index(const RepDev& R, long long k, double2 p, double2 sp, long long& cell) {
+    const double fxc = lattice_qf(p.x, frame_shift(R.sx, k), R.inv_lat);
+    const double fyc = lattice_qf(p.y, frame_shift(R.sy, k), R.inv_lat);
+    const double fxp = lattice_qf(sp.x, frame_shift(R.sx, k - 1), R.inv_lat);
+    const double fyp = lattice_qf(sp.y, frame_shift(R.sy, k - 1), R.inv_lat);
+    // lattice coordinates below 2^29 in magnitude (every run short of ~2^29
+    // cells of frame drift) take 32-bit integers, exactly as the 64-bit path
+    if (fmax(fmax(fabs(fxc), fabs(fyc)), fmax(fabs(fxp), fabs(fyp))) < 536870912.0) {
+        const int lx = R.lx;
+        const int qxc = (int)fxc, qyc = (int)fyc;
+        int vx = qxc - (int)fxp, vy = qyc - (int)fyp;
+        if (2 * vx > lx) vx -= lx; else if (2 * vx < -lx) vx += lx;
+        if (2 * vy > lx) vy -= lx; else if (2 * vy < -lx) vy += lx;
+        int idx = MDLG_NQ;
+        if (vx >= -3 && vx <= 3 && vy >= -3 && vy <= 3) idx = d_lut.idx[(vy + 3) * 7 + (vx + 3)];
+        int cxm = qxc, cym = qyc;
+        if (cxm < 0 || cxm >= lx) { cxm %= lx; if (cxm < 0) cxm += lx; }
+        if (cym < 0 || cym >= lx) { cym %= lx; if (cym < 0) cym += lx; }
+        cell = (long long)cym * lx + cxm;
+        return idx;
+    }
     const long long lx = R.lx;
-    const long long qxc = lattice_q(p.x, frame_shift(R.sx, k), R.inv_lat);
-    const long long qyc = lattice_q(p.y, frame_shift(R.sy, k), R.inv_lat);
-    const long long qxp = lattice_q(sp.x, frame_shift(R.sx, k - 1), R.inv_lat);
-    const long long qyp = lattice_q(sp.y, frame_shift(R.sy, k - 1), R.inv_lat);
-    long long vx = qxc - qxp, vy = qyc - qyp;
+    const long long qxc = (long long)fxc, qyc = (long long)fyc;
+    long long vx = qxc - (long long)fxp, vy = qyc - (long long)fyp;
     // lattice minimum image: a particle that crossed the box edge
     if (2 * vx > lx) vx -= lx; else if (2 * vx < -lx) vx += lx;
     if (2 * vy > lx) vy -= lx; else if (2 * vy < -lx) vy += lx;
@@ -1001,6 +1023,79 @@ constexpr int kPairBuildBS = 256;  // threads of the tile list builder
 constexpr int kPairHashBits = 11;  // its slot table: 2048 buckets
 constexpr int kPairHash = 1 << kPairHashBits;
 
+// End of a coarse step: per replica and component, the fixed-order sum over
+// the replica's tiles of the histogram and moment partials is added to the
+// caller's accumulators.  Block (r, c): c < 50 counts, c >= 50 moments.  Tiles
+// of the step kernel that wrote the partials: mode 0 slot tiles, 1 cell tiles,
+// 2 fused tiles.  Partials are stored component-major, so a block reads one
+// contiguous row; each thread issues its loads (up to kFinishU per chunk of
+// 256 kFinishU tiles) together and sums them in order, then a wave tree and
+// the waves in order finish the block.  Block 0 advances the coarse-step
+// index (no kernel of this launch reads it).  The same code runs as a kernel
+// of its own or in the first blocks of the fused launch after the event (the
+// same sums in the same order either way).
+constexpr int kFinishU = 16;
+constexpr int kFinishBS = 256;  // threads that load and sum (a block may be wider; the rest join the barrier)
+
+__device__ __forceinline__ void cg_finish_one(const int* __restrict__ hpart, const double* __restrict__ mpart,
+                                              int pstride, const RepDev* __restrict__ reps,
+                                              unsigned long long* counts, double* moments, long long* event_k,
+                                              int mode, int blk) {
+    __shared__ double red[4];
+    __shared__ long long redi[4];
+    const int r = blk / (MDLG_NCOUNTS + MDLG_NMOMENTS);
+    const int c = blk % (MDLG_NCOUNTS + MDLG_NMOMENTS);
+    const RepDev& R = reps[r];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const bool act = tid < kFinishBS;
+    const int b0 = mode == 2 ? R.pt0 : (mode == 1 ? R.ttile0 : R.tile0);
+    const int nb = mode == 2 ? R.pnt : (mode == 1 ? R.nttile : R.ntile);
+    if (c < MDLG_NCOUNTS) {
+        const int* __restrict__ row = hpart + (long long)c * pstride + b0;
+        long long sum = 0;
+        if (act) {
+            for (int base = 0; base < nb; base += kFinishBS * kFinishU) {
+                int v[kFinishU];
+#pragma unroll
+                for (int u = 0; u < kFinishU; ++u) {
+                    const int b = base + tid + u * kFinishBS;
+                    v[u] = b < nb ? row[b] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kFinishU; ++u) sum += v[u];
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (act && lane == 0) redi[wv] = sum;
+        __syncthreads();
+        if (tid == 0) {
+            const long long tot = redi[0] + redi[1] + redi[2] + redi[3];
+            if (tot) counts[(long long)r * MDLG_NCOUNTS + c] += (unsigned long long)tot;
+        }
+    } else {
+        const int j = c - MDLG_NCOUNTS;
+        const double* __restrict__ row = mpart + (long long)j * pstride + b0;
+        double sum = 0.0;
+        if (act) {
+            for (int base = 0; base < nb; base += kFinishBS * kFinishU) {
+                double v[kFinishU];
+#pragma unroll
+                for (int u = 0; u < kFinishU; ++u) {
+                    const int b = base + tid + u * kFinishBS;
+                    v[u] = b < nb ? row[b] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kFinishU; ++u) sum += v[u];
+            }
+        }
+        sum = wave_sum(sum);
+        if (act && lane == 0) red[wv] = sum;
+        __syncthreads();
+        if (tid == 0) moments[(long long)r * MDLG_NMOMENTS + j] += ((red[0] + red[1]) + red[2]) + red[3];
+    }
+    if (blk == 0 && tid == 0) *event_k += 1;
+}
+
 // NS ordinary steps of one tile (FIRST: the stored velocity is a full-step one,
 // only as a launch of one step; CG: the last step ends a coarse step, and the
 // owned particles also evaluate the event of Eq.(n_i): lattice index and
@@ -1010,7 +1105,8 @@ constexpr int kPairHash = 1 << kPairHashBits;
 // also binned for its counting sort at their final positions: cell key, rank
 // within the cell by an atomic count, and the drift check against the
 // positions of the list build, the work of k_bin without its pass over the
-// positions).
+// positions).  A launch without an event may also carry the finish of the
+// previous one in its first a.fin_n blocks, after their tile.
 template <int BS, bool F32, int NS, bool FIRST, bool CG, bool BIN>
 __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
     static_assert(NS >= 1 && NS <= 3 && (!FIRST || NS == 1), "one to three steps; a first step alone");
@@ -1195,6 +1291,11 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
             a.mpart[(long long)(1 + tid) * a.pstride + t] = sum;
         }
         if (tid == 0) a.mpart[t] = 2.0 * (double)own;
+    }
+    if constexpr (!CG) {
+        // the previous event's finish rides on the first blocks of this launch
+        if (a.fin_n > 0 && (int)blockIdx.x < a.fin_n)
+            cg_finish_one(a.hpart, a.mpart, a.pstride, a.reps, a.counts, a.moments, a.event_kw, 2, blockIdx.x);
     }
 }
 
@@ -1408,69 +1509,12 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     }
 }
 
-// End of a coarse step: per replica and component, the fixed-order sum over
-// the replica's tiles of the histogram and moment partials is added to the
-// caller's accumulators.  Block (r, c): c < 50 counts, c >= 50 moments.  Tiles
-// of the step kernel that wrote the partials: mode 0 slot tiles, 1 cell tiles,
-// 2 fused tiles.  Partials are stored component-major, so a block reads one
-// contiguous row; each thread issues its loads (up to kFinishU per chunk of
-// 256 kFinishU tiles) together and sums them in order, then a wave tree and
-// the waves in order finish the block.  Block 0 advances the coarse-step
-// index (no kernel of this launch reads it).
-constexpr int kFinishU = 16;
-
-__global__ __launch_bounds__(256) void k_cg_finish(const int* __restrict__ hpart, const double* __restrict__ mpart,
-                                                   int pstride, const RepDev* __restrict__ reps,
-                                                   unsigned long long* counts, double* moments, long long* event_k,
-                                                   int mode) {
-    __shared__ double red[4];
-    __shared__ long long redi[4];
-    const int r = blockIdx.x / (MDLG_NCOUNTS + MDLG_NMOMENTS);
-    const int c = blockIdx.x % (MDLG_NCOUNTS + MDLG_NMOMENTS);
-    const RepDev& R = reps[r];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int b0 = mode == 2 ? R.pt0 : (mode == 1 ? R.ttile0 : R.tile0);
-    const int nb = mode == 2 ? R.pnt : (mode == 1 ? R.nttile : R.ntile);
-    if (c < MDLG_NCOUNTS) {
-        const int* __restrict__ row = hpart + (long long)c * pstride + b0;
-        long long sum = 0;
-        for (int base = 0; base < nb; base += 256 * kFinishU) {
-            int v[kFinishU];
-#pragma unroll
-            for (int u = 0; u < kFinishU; ++u) {
-                const int b = base + tid + u * 256;
-                v[u] = b < nb ? row[b] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kFinishU; ++u) sum += v[u];
-        }
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        if (lane == 0) redi[wv] = sum;
-        __syncthreads();
-        if (tid == 0) {
-            const long long tot = redi[0] + redi[1] + redi[2] + redi[3];
-            if (tot) counts[(long long)r * MDLG_NCOUNTS + c] += (unsigned long long)tot;
-        }
-    } else {
-        const int j = c - MDLG_NCOUNTS;
-        const double* __restrict__ row = mpart + (long long)j * pstride + b0;
-        double sum = 0.0;
-        for (int base = 0; base < nb; base += 256 * kFinishU) {
-            double v[kFinishU];
-#pragma unroll
-            for (int u = 0; u < kFinishU; ++u) {
-                const int b = base + tid + u * 256;
-                v[u] = b < nb ? row[b] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kFinishU; ++u) sum += v[u];
-        }
-        sum = wave_sum(sum);
-        if (lane == 0) red[wv] = sum;
-        __syncthreads();
-        if (tid == 0) moments[(long long)r * MDLG_NMOMENTS + j] += ((red[0] + red[1]) + red[2]) + red[3];
-    }
-    if (blockIdx.x == 0 && tid == 0) *event_k += 1;
+// The finish as a kernel of its own (one block per replica and component).
+__global__ __launch_bounds__(kFinishBS) void k_cg_finish(const int* __restrict__ hpart, const double* __restrict__ mpart,
+                                                         int pstride, const RepDev* __restrict__ reps,
+                                                         unsigned long long* counts, double* moments,
+                                                         long long* event_k, int mode) {
+    cg_finish_one(hpart, mpart, pstride, reps, counts, moments, event_k, mode, blockIdx.x);
 }
 
 // Observation at the current positions: forces, full-step velocities, state
@@ -1872,6 +1916,7 @@ struct lj_md {
     bool vel_full = true;
     bool have_cellof = false;
     bool binned = false;  // key and cnt hold the current positions' binning (done by the last step launch)
+    bool fin_pending = false;  // the last event's partials await their finish (see launch_fused)
     bool broken = false;
     int K = 50;
     bool K_auto = true;
@@ -2000,8 +2045,23 @@ void launch_step_kernel(const lj_md* md, hipStream_t st, const StepArgs& a, hipE
     }
 }
 
+// The finish of an event whose partials are still pending, as a kernel of
+// its own: before anything reads the accumulators or the event counter, and
+// at the end of every run of launches (so that no pending finish outlives a
+// captured graph or a call).
+hipError_t flush_finish(lj_md* md, hipStream_t st) {
+    if (!md->fin_pending) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_finish, dim3(md->R * (MDLG_NCOUNTS + MDLG_NMOMENTS)), dim3(kFinishBS), 0, st,
+                       (const int*)md->d_hpart, (const double*)md->d_mpart, md->pstride, (const RepDev*)md->d_reps,
+                       md->counts, md->moments, md->d_event_k, 2);
+    md->fin_pending = false;
+    return hipGetLastError();
+}
+
 hipError_t launch_step(lj_md* md, hipStream_t st, bool first, bool cg, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr) {
+    hipError_t fe = flush_finish(md, st);
+    if (fe != hipSuccess) return fe;
     StepArgs a = make_args(md);
     if (md->f32) {
         if (first) {
@@ -2061,16 +2121,25 @@ void launch_fused_f(hipStream_t st, int grid, const StepArgs& a, int ns, bool fi
 // reduction when `cg`, binning the particles for the next rebuild when `bin`.
 hipError_t launch_fused(lj_md* md, hipStream_t st, int ns, bool first, bool cg, bool bin) {
     StepArgs a = make_args(md);
+    // a pending finish goes with this launch unless it is an event itself
+    // (whose partials would overwrite the pending ones) or has fewer blocks
+    // than the finish
+    const int fin_n = md->R * (MDLG_NCOUNTS + MDLG_NMOMENTS);
+    hipError_t e = hipSuccess;
+    if (md->fin_pending && (cg || fin_n > md->npt)) e = flush_finish(md, st);
+    if (e != hipSuccess) return e;
+    if (md->fin_pending) {
+        a.fin_n = fin_n;
+        a.moments = md->moments;
+        a.event_kw = md->d_event_k;
+    }
     if (md->f32) launch_fused_f<true>(st, md->npt, a, ns, first, cg, bin);
     else launch_fused_f<false>(st, md->npt, a, ns, first, cg, bin);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (cg) {
-        hipLaunchKernelGGL(k_cg_finish, dim3(md->R * (MDLG_NCOUNTS + MDLG_NMOMENTS)), dim3(256), 0, st,
-                           (const int*)md->d_hpart, (const double*)md->d_mpart, md->pstride, (const RepDev*)md->d_reps,
-                           md->counts, md->moments, md->d_event_k, 2);
-        e = hipGetLastError();
-    }
+    if (a.fin_n) md->fin_pending = false;
+    // this event's finish rides on the next launch, or flush_finish issues it
+    if (cg) md->fin_pending = true;
     md->ppar ^= 1;
     md->vpar ^= 1;
     return e;
@@ -2227,6 +2296,7 @@ hipError_t run_steps(lj_md* md, hipStream_t st, long long count) {
         e = issue(md, st, p);
         count -= p.n;
     }
+    if (e == hipSuccess) e = flush_finish(md, st);
     return e;
 }
 
@@ -2755,12 +2825,14 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                 status = capture(md, [&](hipStream_t cs) {
                     hipError_t e = hipSuccess;
                     for (size_t i = 0; i < lead && e == hipSuccess; ++i) e = issue(md, cs, plan[i]);
+                    if (e == hipSuccess) e = flush_finish(md, cs);
                     return e;
                 }, &G.g[1]);
             if (status == MDLG_OK && lead < plan.size())
                 status = capture(md, [&](hipStream_t cs) {
                     hipError_t e = hipSuccess;
                     for (size_t i = lead; i < plan.size() && e == hipSuccess; ++i) e = issue(md, cs, plan[i]);
+                    if (e == hipSuccess) e = flush_finish(md, cs);
                     return e;
                 }, &G.g[2]);
             G.tail_events = (int)(md->events - ev0);
