@@ -68,11 +68,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Lattice coordinate floor((x + shift) * inv), every operation rounded once,
 // exactly as written (no fused multiply-add), so that host and device agree
 // on the cell of a position bit for bit.
-__device__ __forceinline__ long long lattice_q(double x, double shift, double inv) {
+__device__ __forceinline__ double lattice_qf(double x, double shift, double inv) {
 #pragma clang fp contract(off)
     double t = x + shift;
     double u = t * inv;
-    return (long long)floor(u);
+    return floor(u);
+}
+
+__device__ __forceinline__ long long lattice_q(double x, double shift, double inv) {
+    return (long long)lattice_qf(x, shift, inv);
 }
 
 __device__ __forceinline__ double frame_shift(double per_step, long long k) {
