@@ -546,3 +546,47 @@ def test_save_and_resume(tmp_path):
         ua, ub = pa[sl] + L * ia[sl], pb[sl] + L * ib[sl]
         assert np.max(np.abs(ua - ub)) <= 1e-9 * L
         assert np.max(np.abs(va[sl] - vb[sl])) <= 1e-8 * np.max(np.abs(va[sl]))
+
+
+def test_event_finish_placement_keeps_the_counts():
+    """The finish of a coarse-graining event runs in the first blocks of the
+    next launch, or as a kernel of its own before another event and at the
+    end of every call.  Runs that end calls at events, between them and at
+    whole cell-list intervals (timed graphs) give the same counts and steps;
+    the moments agree to rounding (the launch plans differ).  121 fused tiles,
+    more than the finish's 55 blocks, so the finish can ride on a launch."""
+    import torch
+    n, phi, kT, lx, s_cg = 32768, 0.0784, 20.0, 128, 50
+    pos0, vel0, L = mi.initial_state(n, phi, kT, 5)
+    out = []
+    for mode in ("one call", "ragged calls", "timed units"):
+        print(f"finish placement: {mode}", flush=True)
+        sysm = gpu_system(pos0, vel0, L)
+        assert sysm.info()["steps_per_launch"] == 3
+        acc = sysm.attach_cg(lx, s_cg)
+        if mode == "one call":
+            sysm.step(1000)
+        elif mode == "ragged calls":
+            left = 1000
+            for k in range(1000):
+                c = min(left, (7, 50, 3, 43, 97)[k % 5])
+                sysm.step(c)
+                left -= c
+                if not left:
+                    break
+        else:
+            # the first launches, then whole intervals (the timed call aligns
+            # the event phase first), then the rest
+            sysm.step(50)
+            K = sysm.info()["rebuild_every"]
+            sysm.step_timed((1000 - 50 - K) // K)
+            sysm.step(1000 - sysm.info()["steps_done"])
+        torch.cuda.synchronize()
+        sysm.check()
+        assert sysm.info()["steps_done"] == 1000
+        assert acc.events == 1000 // s_cg
+        out.append((_np(acc.counts)[0].copy(), _np(acc.moments)[0].copy()))
+        sysm.close()
+    for c, mo in out[1:]:
+        assert np.array_equal(c, out[0][0])
+        assert_moments_close(mo, out[0][1])
