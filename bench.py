@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--seeds", type=int, default=4, help="precision: seeds")
     ap.add_argument("--precision-steps", type=int, default=10000, help="precision: MD steps per run")
     ap.add_argument("--replicas", type=int, default=256)
-    ap.add_argument("--train-steps", type=int, default=100000, help="surrogate: Adam steps")
+    ap.add_argument("--train-steps", type=int, default=200000, help="surrogate: Adam steps")
     ap.add_argument("--train-batch", type=int, default=2048, help="surrogate: minibatch")
     ap.add_argument("--groups", type=int, default=4, help="surrogate: replica groups (80 replicas each)")
     ap.add_argument("--paper-replicas", type=int, default=4, help="paper: independent systems of 99,856 particles")
