@@ -10,9 +10,11 @@ velocities; seed 0).
 One benchmark step = one coarse time step: s_cg MD steps, each one fused
 force + velocity-Verlet kernel, the last one also evaluating the coarse-
 graining event, plus the cell-list rebuilds on their schedule, replayed from
-captured HIP graphs (one cell-list interval as three graphs, with HIP events
-between them that give the kernel times of the same run).  `value` is
-particle-steps/s of the whole job, with the state resident in HBM.
+captured HIP graphs: one cell-list interval in every SAMPLE_EVERY as three
+graphs with HIP events between them (the kernel times of the same run), the
+others as one graph each (a graph boundary costs the device ~15 us, so
+splitting every interval would cost the job ~5%).  `value` is particle-steps/s
+of the whole job, with the state resident in HBM.
 
 Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
 """
@@ -213,16 +215,25 @@ def gpu_feq_vs_oracle(m, torch, pos0, vel0, L, lx, s_cg, steps, force_bits, ocou
             "reference": "the oracle (FP64 CPU) from the same initial state"}
 
 
+SAMPLE_EVERY = 4  # cell-list intervals per timed sample (split into three graphs)
+
+
+def sample_every(units):
+    return max(1, min(SAMPLE_EVERY, units // 3))
+
+
 def timed_reps(sysm, units, reps, torch):
     """`reps` repetitions of `units` cell-list intervals, each bracketed by HIP
-    events on the launch stream; returns [(ms, kernel ms [3], launches [3])]."""
+    events on the launch stream (every sample_every(units)-th interval split
+    into three graphs for the kernel times); returns [(ms, kernel ms [3],
+    launches [3])]."""
     out = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        kms, kcnt = sysm.step_timed(units)
+        kms, kcnt = sysm.step_timed(units, sample_every(units))
         e1.record()
         torch.cuda.synchronize()
         out.append((e0.elapsed_time(e1), [float(x) for x in kms], [int(x) for x in kcnt]))
@@ -234,7 +245,7 @@ def warm(sysm, units, seconds, torch):
     clocks of a loaded GPU settle below those of a short burst)."""
     t0 = time.perf_counter()
     while True:
-        sysm.step_timed(units)
+        sysm.step_timed(units, sample_every(units))
         torch.cuda.synchronize()
         if time.perf_counter() - t0 >= seconds:
             return time.perf_counter() - t0
@@ -371,6 +382,7 @@ def bench_single(args):
                    "block_size": info["block_size"]},
         "timing": {"repetitions": args.reps, "md_steps_per_repetition": md_steps,
                    "ms_per_repetition": [r_[0] for r_ in reps], "value_from": "median repetition",
+                   "split_interval_every": sample_every(units),
                    "warmup_s": warm_s, "steps_before_timing": int(steps_before)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -160,19 +160,24 @@ mdlg_status lj_md_cg_detach(lj_md* md);
 mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream);
 
 /* Advance the replicas by nunits x rebuild_every MD steps like lj_md_step,
- * timing the kernels as the captured graphs run them: each unit (one
- * cell-list interval) is replayed as three graphs with HIP events on
- * `stream` between them: the cell rebuild, the ordinary steps before the
- * unit's first coarse-graining step, and the remaining steps.  ms_out (host
- * [3]) receives the device time per launch of [0] an ordinary step kernel
- * (the ordinary steps' graph time over their number), [1] a coarse-graining
- * step with its reduction (the last graph's time less its ordinary steps)
- * and [2] a cell rebuild, each averaged over the counted units; n_out (host
- * [3], may be NULL) the number of kernels or graphs behind each.  The graphs
- * stay in the handle for later calls; units up to the last one whose graphs
- * were captured in this call warm up (capture leaves the GPU idle) and are
- * not counted.  nunits >= 3.  Synchronises `stream`. */
-mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_out, int32_t* n_out, void* stream);
+ * timing the kernels as the captured graphs run them: every sample_every-th
+ * unit (one cell-list interval; the first of the call included) is replayed
+ * as three graphs with HIP events on `stream` between them: the cell
+ * rebuild, the ordinary steps before the unit's first coarse-graining step,
+ * and the remaining steps; the other units run as one graph each, as
+ * lj_md_step runs them (a graph boundary costs the device ~15 us, so
+ * sampling keeps the timing's own cost small).  ms_out (host [3]) receives
+ * the device time per launch of [0] an ordinary step kernel (the ordinary
+ * steps' graph time over their number), [1] a coarse-graining step with
+ * the launches after it in its unit (the last graph's time less its
+ * ordinary steps, per event) and [2] a cell rebuild, each averaged over the
+ * counted sampled units; n_out (host [3], may be NULL) the number of kernels
+ * or graphs behind each.  The graphs stay in the handle for later calls;
+ * sampled units up to the last capture of this call warm up (capture
+ * leaves the GPU idle) and are not counted.  nunits >= 3, sample_every in
+ * [1, nunits / 3] (above 1 only with graph replay).  Synchronises `stream`. */
+mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, int32_t sample_every, double* ms_out, int32_t* n_out,
+                             void* stream);
 
 /* Copy the state out in the caller's particle order (index = position in
  * pos0).  Any output may be NULL.  pos, vel: device [n_total][2] float64

@@ -163,12 +163,13 @@ def lj_md_step(h, nsteps, stream=None):
     _abi.check(_abi.lib().lj_md_step(h, int(nsteps), _stream(stream)))
 
 
-def lj_md_step_timed(h, nunits, stream=None):
-    """Advance nunits cell-list intervals, timing the graphs.  Returns (avg ms [3], counts [3]) for
-    [ordinary step kernel, coarse-graining step with its reduction, cell-list rebuild]."""
+def lj_md_step_timed(h, nunits, stream=None, sample_every=1):
+    """Advance nunits cell-list intervals, timing every sample_every-th one as split graphs.  Returns
+    (avg ms [3], counts [3]) for [ordinary step kernel, coarse-graining step with the launches after it,
+    cell-list rebuild]."""
     ms = np.zeros(3)
     cnt = np.zeros(3, np.int32)
-    _abi.check(_abi.lib().lj_md_step_timed(h, int(nunits), ms.ctypes.data_as(C.c_void_p),
+    _abi.check(_abi.lib().lj_md_step_timed(h, int(nunits), int(sample_every), ms.ctypes.data_as(C.c_void_p),
                                            cnt.ctypes.data_as(C.c_void_p), _stream(stream)))
     return ms, cnt
 
@@ -673,8 +674,8 @@ class LJSystem:
     def step(self, nsteps):
         lj_md_step(self.handle, nsteps, self.stream)
 
-    def step_timed(self, nunits):
-        return lj_md_step_timed(self.handle, nunits, self.stream)
+    def step_timed(self, nunits, sample_every=1):
+        return lj_md_step_timed(self.handle, nunits, self.stream, sample_every)
 
     def state(self):
         torch = _torch()

@@ -116,7 +116,7 @@ def lib() -> C.CDLL:
         "lj_md_cg_attach": (i32, [vp, i32, P(Lattice), vp, vp, vp, vp]),
         "lj_md_cg_detach": (i32, [vp]),
         "lj_md_step": (i32, [vp, i64, vp]),
-        "lj_md_step_timed": (i32, [vp, i64, vp, vp, vp]),
+        "lj_md_step_timed": (i32, [vp, i64, i32, vp, vp, vp]),
         "lj_md_get_state": (i32, [vp, vp, vp, vp, vp]),
         "lj_md_forces": (i32, [vp, vp, vp]),
         "lj_md_energy": (i32, [vp, vp, vp]),

@@ -55,7 +55,7 @@ double time_config(int n_rep, const std::vector<lj_params>& p, const double* pos
     }
     double ms[3] = {0, 0, 0};
     int32_t cnt[3] = {0, 0, 0};
-    *st = lj_md_step_timed(md, units, ms, cnt, stream);
+    *st = lj_md_step_timed(md, units, 1, ms, cnt, stream);
     lj_md_info_t info{};
     if (*st == MDLG_OK) *st = lj_md_check(md, stream);
     if (*st == MDLG_OK) *st = lj_md_info(md, &info);

@@ -1848,10 +1848,15 @@ struct RepHost {
     int nslots;
 };
 
+// Cell-list intervals captured into one graph by lj_md_step when at least
+// that many remain.
+constexpr int kGraphUnits = 4;
+
 struct GraphKey {
-    int K, phase, ppar, opar, vpar, binned;
+    int K, phase, ppar, opar, vpar, binned, units;
     bool operator<(const GraphKey& o) const {
-        return std::tie(K, phase, ppar, opar, vpar, binned) < std::tie(o.K, o.phase, o.ppar, o.opar, o.vpar, o.binned);
+        return std::tie(K, phase, ppar, opar, vpar, binned, units) <
+               std::tie(o.K, o.phase, o.ppar, o.opar, o.vpar, o.binned, o.units);
     }
 };
 
@@ -2331,15 +2336,29 @@ int unit_phase(const lj_md* md) {
     return to_event <= md->K ? (int)to_event : 0;
 }
 
-// rebuild + K steps, replayed from a captured graph.
-mdlg_status graph_unit(lj_md* md, hipStream_t st) {
-    GraphKey key{md->K, unit_phase(md), md->ppar, md->opar, md->vpar, md->binned ? 1 : 0};
+// Whether several units may share a graph: the launches of later units follow
+// from the first unit's exact coarse-step residue, and the residues repeat
+// with a short period only when one of K and s_cg divides the other.
+bool multi_unit_ok(const lj_md* md) {
+    if (!md->cg_on) return true;
+    return md->s_cg <= md->K ? md->K % md->s_cg == 0 : md->s_cg % md->K == 0;
+}
+
+// `units` x (rebuild + K steps), replayed from a captured graph.  One unit is
+// keyed by unit_phase (units without an event share a graph); several units
+// by the exact coarse-step residue, which fixes every later unit's events.
+mdlg_status graph_unit(lj_md* md, hipStream_t st, int units = 1) {
+    const int phase = units > 1 && md->cg_on ? (int)(md->cg_t % md->s_cg) : unit_phase(md);
+    GraphKey key{md->K, phase, md->ppar, md->opar, md->vpar, md->binned ? 1 : 0, units};
     auto it = md->graphs.find(key);
     if (it == md->graphs.end()) {
         const long long steps0 = md->steps_done, cg_t0 = md->cg_t, ev0 = md->events;
         MDLG_HIP(hipStreamBeginCapture(md->cap, hipStreamCaptureModeThreadLocal));
-        hipError_t e = launch_rebuild(md, md->cap);
-        if (e == hipSuccess) e = run_steps(md, md->cap, md->K);
+        hipError_t e = hipSuccess;
+        for (int u = 0; u < units && e == hipSuccess; ++u) {
+            e = launch_rebuild(md, md->cap);
+            if (e == hipSuccess) e = run_steps(md, md->cap, md->K);
+        }
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(md->cap, &g);
         if (e != hipSuccess) return fail(MDLG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -2364,11 +2383,11 @@ mdlg_status graph_unit(lj_md* md, hipStream_t st) {
     md->opar = it->second.opar_after;
     md->vpar = it->second.vpar_after;
     md->binned = it->second.binned_after;
-    md->steps_done += md->K;
+    md->steps_done += (long long)units * md->K;
     md->since_rebuild = md->K;
     md->have_cellof = true;
     if (md->cg_on) {
-        md->cg_t += md->K;
+        md->cg_t += (long long)units * md->K;
         md->events += it->second.events;
     }
     return MDLG_OK;
@@ -2750,9 +2769,12 @@ extern "C" mdlg_status lj_md_step(lj_md* md, int64_t nsteps, void* stream) {
     while (nsteps > 0) {
         const long long n = eager_len(md, nsteps);
         if (n == 0) {
-            mdlg_status s = graph_unit(md, st);
+            // whole intervals, kGraphUnits to a graph where they fill one (each
+            // graph boundary costs the device ~15 us)
+            const int units = nsteps >= (long long)kGraphUnits * md->K && multi_unit_ok(md) ? kGraphUnits : 1;
+            mdlg_status s = graph_unit(md, st, units);
             if (s != MDLG_OK) return s;
-            nsteps -= md->K;
+            nsteps -= (long long)units * md->K;
             continue;
         }
         hipError_t e = run_steps(md, st, n);
@@ -2782,10 +2804,15 @@ mdlg_status capture(lj_md* md, F fn, hipGraphExec_t* out) {
 
 }  // namespace
 
-extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_out, int32_t* n_out, void* stream) {
+extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, int32_t sample_every, double* ms_out,
+                                        int32_t* n_out, void* stream) {
     if (!md || !ms_out) return fail(MDLG_EINVAL, "lj_md_step_timed: NULL argument");
     if (md->broken) return fail(MDLG_EINVAL, "lj_md_step_timed: handle is unusable after a device fault");
     if (nunits < 3 || nunits > 10000) return fail(MDLG_EINVAL, "lj_md_step_timed: nunits must be in [3, 1e4]");
+    if (sample_every < 1 || sample_every > nunits / 3)
+        return fail(MDLG_EINVAL, "lj_md_step_timed: sample_every must be in [1, nunits / 3]");
+    if (!md->use_graphs && sample_every > 1)
+        return fail(MDLG_EINVAL, "lj_md_step_timed: sample_every > 1 needs graph replay");
     hipStream_t st = (hipStream_t)stream;
     // direct launches up to the first interval aligned with the coarse steps
     while (md->vel_full || steps_to_alignment(md) > 0) {
@@ -2806,6 +2833,16 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
     std::vector<UnitRec> order;
     mdlg_status status = MDLG_OK;
     for (int64_t u = 0; u < nunits && status == MDLG_OK; ++u) {
+        if (u % sample_every != 0) {
+            // the units up to the next sampled one (or the end): one graph
+            // (rebuilds + their K steps each), as lj_md_step runs them
+            const int run = multi_unit_ok(md) ? (int)std::min<int64_t>(sample_every - u % sample_every, nunits - u) : 1;
+            const size_t cached = md->graphs.size();
+            status = graph_unit(md, st, run);
+            if (md->graphs.size() != cached) last_capture = (int)order.size() - 1;
+            u += run - 1;
+            continue;
+        }
         const int phase = unit_phase(md);
         const auto key = std::make_tuple(K, md->ppar, md->opar, md->vpar, phase, md->binned ? 1 : 0);
         auto it = cache.find(key);
@@ -2846,7 +2883,7 @@ extern "C" mdlg_status lj_md_step_timed(lj_md* md, int64_t nunits, double* ms_ou
                 break;
             }
             cache[key] = G;
-            last_capture = (int)u;
+            last_capture = (int)order.size();  // this unit's record
             // captures only recorded work: restore the step counters
             md->ppar = std::get<1>(key);
             md->opar = std::get<2>(key);

@@ -579,7 +579,7 @@ def test_event_finish_placement_keeps_the_counts():
             # the event phase first), then the rest
             sysm.step(50)
             K = sysm.info()["rebuild_every"]
-            sysm.step_timed((1000 - 50 - K) // K)
+            sysm.step_timed((1000 - 50 - K) // K, 3)  # every third interval split into timed graphs
             sysm.step(1000 - sysm.info()["steps_done"])
         torch.cuda.synchronize()
         sysm.check()
