@@ -10,7 +10,7 @@ velocities; seed 0).
 One benchmark step = one coarse time step: s_cg MD steps, each one fused
 force + velocity-Verlet kernel, the last one also evaluating the coarse-
 graining event, plus the cell-list rebuilds on their schedule, replayed from
-captured HIP graphs: one cell-list interval in every SAMPLE_EVERY as three
+captured HIP graphs: one cell-list interval in every SAMPLE_EVERY (8) as three
 graphs with HIP events between them (the kernel times of the same run), the
 others as one graph each (a graph boundary costs the device ~15 us, so
 splitting every interval would cost the job ~5%).  `value` is particle-steps/s
@@ -215,7 +215,7 @@ def gpu_feq_vs_oracle(m, torch, pos0, vel0, L, lx, s_cg, steps, force_bits, ocou
             "reference": "the oracle (FP64 CPU) from the same initial state"}
 
 
-SAMPLE_EVERY = 4  # cell-list intervals per timed sample (split into three graphs)
+SAMPLE_EVERY = 8  # cell-list intervals per timed sample (split into three graphs)
 
 
 def sample_every(units):

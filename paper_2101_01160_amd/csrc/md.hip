@@ -1850,7 +1850,7 @@ struct RepHost {
 
 // Cell-list intervals captured into one graph by lj_md_step when at least
 // that many remain.
-constexpr int kGraphUnits = 4;
+constexpr int kGraphUnits = 8;
 
 struct GraphKey {
     int K, phase, ppar, opar, vpar, binned, units;
