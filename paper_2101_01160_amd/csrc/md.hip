@@ -1409,8 +1409,8 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     // but the last) reordered by the particle's number of list-row groups
     // (kListU rows each), most first, so that the lanes of a wave mostly run
     // the same number of passes over their lists.  Within a group the order is
-    // that of LDS atomics: it moves staged indices, not results (each
-    // particle still sums its own list in list order).  An LDS table maps
+    // the segment order (a stable counting sort), so every per-tile sum over
+    // the staged particles rounds the same way in every run.  An LDS table maps
     // slot -> staged index (open addressing, kPairHash buckets for at most
     // kPairCap keys, so a probe always reaches an empty bucket).
     __shared__ int hkey[kPairHash];  // slot + 1; 0: empty
@@ -1437,12 +1437,25 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         while (q >= n[r]) ++r;
         return r;
     };
-    for (int q = threadIdx.x; q < listed; q += BS) {
-        const int nn = nbc[lq0[q]];
-        const int g = (nn + kListU - 1) / kListU;
-        cntq[q] = (unsigned char)nn;
-        gq[q] = (unsigned char)g;
-        atomicAdd(&gcnt[ring_of(q)][g], 1);
+    // group counts per ring, and per 64-particle chunk one ballot of each bit
+    // of the group number (every wave's lanes cover one chunk at a time)
+    static_assert(kGroups == 128, "group numbers have 7 bits");
+    const int nbits = ng > 1 ? 32 - __clz(ng - 1) : 0;
+    __shared__ unsigned long long gbit[kPairCap / 64][7];
+    for (int base = threadIdx.x & ~63; base < listed; base += BS) {
+        const int q = base + (threadIdx.x & 63);
+        int g = 0;
+        if (q < listed) {
+            const int nn = nbc[lq0[q]];
+            g = (nn + kListU - 1) / kListU;
+            cntq[q] = (unsigned char)nn;
+            gq[q] = (unsigned char)g;
+            atomicAdd(&gcnt[ring_of(q)][g], 1);
+        }
+        for (int b = 0; b < nbits; ++b) {
+            const unsigned long long m = __ballot((g >> b) & 1);
+            if ((threadIdx.x & 63) == 0) gbit[base >> 6][b] = m;
+        }
     }
     __syncthreads();
     if (threadIdx.x < rings) {  // first staged index of each (ring, group), most groups first
@@ -1457,8 +1470,26 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     __syncthreads();
     auto bucket = [](int k) { return ((unsigned int)k * 2654435761u) >> (32 - kPairHashBits); };
     int* list = plist + (long long)t * kPairCap;
+    // A listed particle's place: its group's first index plus the number of
+    // earlier particles of the same ring and group in segment order, counted
+    // chunk by chunk from the group-bit ballots over the ring's range, so that
+    // the staged order does not depend on the timing of atomics.
+    auto below = [](int e) { return e >= 64 ? ~0ull : (1ull << e) - 1ull; };
     for (int q = threadIdx.x; q < tot; q += BS) {
-        const int qn = q < listed ? atomicAdd(&gcnt[ring_of(q)][gq[q]], 1) : q;
+        int qn = q;
+        if (q < listed) {
+            const int r = ring_of(q), g = gq[q];
+            const int lo = r == 0 ? 0 : n[r - 1], hi = n[r], c = q >> 6;
+            int rank = gcnt[r][g];
+            for (int cc = lo >> 6; cc <= c; ++cc) {
+                const int a = min(max(lo - cc * 64, 0), 64);
+                const int e = cc == c ? (q & 63) : min(max(hi - cc * 64, 0), 64);
+                unsigned long long m = below(e) & ~below(a);
+                for (int b = 0; b < nbits; ++b) m &= ((g >> b) & 1) ? gbit[cc][b] : ~gbit[cc][b];
+                rank += __popcll(m);
+            }
+            qn = rank;
+        }
         const int slot = lq0[q];
         lq[qn] = slot;
         list[qn] = slot;

@@ -590,3 +590,33 @@ def test_event_finish_placement_keeps_the_counts():
     for c, mo in out[1:]:
         assert np.array_equal(c, out[0][0])
         assert_moments_close(mo, out[0][1])
+
+
+@pytest.mark.parametrize("s_cg", [25, 50, 100])
+def test_several_intervals_per_graph_equal_one_at_a_time(s_cg):
+    """lj_md_step captures eight cell-list intervals to a graph where the
+    coarse-step residue fixes their events (one of K and s_cg divides the
+    other); the state, counts and moments equal those of calls of one
+    interval each, bit for bit (the same launches in the same order)."""
+    import torch
+    n, phi, kT = 20000, 0.0784, 20.0
+    pos0, vel0, L = mi.initial_state(n, phi, kT, 9)
+    lx = int(L / 4.0)
+    out = []
+    for chunk in (1200, None):
+        sysm = gpu_system(pos0, vel0, L, rebuild_every=50)
+        acc = sysm.attach_cg(lx, s_cg)
+        if chunk:
+            sysm.step(chunk)
+        else:
+            sysm.step(2)  # the first launch and the alignment, then one interval per call
+            while sysm.info()["steps_done"] + 50 <= 1200:
+                sysm.step(50)
+            sysm.step(1200 - sysm.info()["steps_done"])
+        torch.cuda.synchronize()
+        sysm.check()
+        assert sysm.info()["steps_done"] == 1200 and acc.events == 1200 // s_cg
+        out.append([_np(t) for t in sysm.state()] + [_np(acc.counts), _np(acc.moments)])
+        sysm.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
