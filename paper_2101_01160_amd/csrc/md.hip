@@ -728,13 +728,17 @@ __device__ __forceinline__ bool within_list_range(double dx, double dy, double r
 // An entry is the neighbour's slot relative to the particle's own slot,
 // reduced modulo the replica's particle count into [-n/2, n/2): in cell order
 // a neighbour lies within about three cell rows (also across the periodic
-// edge, after the reduction), which fits 16 bits; counts fit 8 bits.  Also
-// records the positions of the build for the next drift check.
+// edge, after the reduction), which fits 16 bits; counts fit 8 bits.  With
+// CELL (for the tile list builder) an entry is instead the neighbour's cell
+// relative to the particle's, (oy + 1) 3 + (ox + 1) in bits 12-15, and its
+// index within that cell in bits 0-11, and ncol[s] holds the particle's cell
+// column.  Also records the positions of the build for the next drift check.
+template <bool CELL>
 __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__ pos, const int* __restrict__ cs,
                                                      const RepDev* __restrict__ reps, const int* __restrict__ tile_rep,
                                                      int BSt, int S, int maxnb, short* __restrict__ nbl,
-                                                     unsigned char* __restrict__ nbc, double2* __restrict__ pref,
-                                                     int* err) {
+                                                     unsigned char* __restrict__ nbc, unsigned short* __restrict__ ncol,
+                                                     double2* __restrict__ pref, int* err) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     const RepDev& R = reps[tile_rep[s / BSt]];
@@ -749,6 +753,7 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
     const double rl2 = R.w * R.w;
     const int cx = cell_coord(p.x, R.inv_w, nc);
     const int cy = cell_coord(p.y, R.inv_w, nc);
+    if (CELL) ncol[s] = (unsigned short)cx;
     int cnt = 0;
     for (int oy = -1; oy <= 1; ++oy) {
         int rw = cy + oy;
@@ -761,6 +766,9 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
         const int xw = cx == 0 ? nc - 1 : 0;
         const int a0 = cs[base + xl], a1 = cs[base + xr];
         const int b0 = wrap ? cs[base + xw] : 0, b1 = wrap ? cs[base + xw + 1] : 0;
+        // with CELL, the first slots of the range's second and third cells
+        const int m1 = CELL && xr - xl >= 2 ? cs[base + xl + 1] : a1;
+        const int m2 = CELL && xr - xl >= 3 ? cs[base + xl + 2] : a1;
         const int na = a1 - a0, tot = na + (b1 - b0);
         for (int t = 0; t < tot; ++t) {
             const int k = t < na ? a0 + t : b0 + (t - na);
@@ -769,11 +777,27 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
             const double dx = min_image_rint(p.x - q.x, R.L, invL);
             const double dy = min_image_rint(p.y - q.y, R.L, invL);
             if (within_list_range(dx, dy, rl2)) {
-                int d = k - s;
-                if (2 * d >= R.n) d -= R.n;
-                else if (2 * d < -R.n) d += R.n;
-                if (d < -32768 || d > 32767) atomicOr(err, ERR_NLIST);
-                if (cnt < maxnb) nbl[(long long)cnt * S + s] = (short)d;
+                int e;
+                if (CELL) {
+                    int ox, first;
+                    if (t < na) {
+                        const int j = (k >= m1 ? 1 : 0) + (k >= m2 ? 1 : 0);
+                        ox = xl + j - cx;
+                        first = j == 0 ? a0 : (j == 1 ? m1 : m2);
+                    } else {
+                        ox = cx == 0 ? -1 : 1;
+                        first = b0;
+                    }
+                    const int idx = k - first;
+                    if (idx > 4095) atomicOr(err, ERR_NLIST);
+                    e = (((oy + 1) * 3 + (ox + 1)) << 12) | (idx & 4095);
+                } else {
+                    e = k - s;
+                    if (2 * e >= R.n) e -= R.n;
+                    else if (2 * e < -R.n) e += R.n;
+                    if (e < -32768 || e > 32767) atomicOr(err, ERR_NLIST);
+                }
+                if (cnt < maxnb) nbl[(long long)cnt * S + s] = (short)e;
                 ++cnt;
             }
         }
@@ -1020,8 +1044,6 @@ constexpr int kPairTarget = 520;   // staged particles aimed at when choosing th
 constexpr int kPairTarget3 = 580;  // the same with three rings
 constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248 for pT <= 32, three rings
 constexpr int kPairBuildBS = 256;  // threads of the tile list builder
-constexpr int kPairHashBits = 11;  // its slot table: 2048 buckets
-constexpr int kPairHash = 1 << kPairHashBits;
 
 // End of a coarse step: per replica and component, the fixed-order sum over
 // the replica's tiles of the histogram and moment partials is added to the
@@ -1312,7 +1334,8 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
 template <int BS>
 __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
                                                     const int* __restrict__ ptrep, const short* __restrict__ nbl,
-                                                    const unsigned char* __restrict__ nbc, int S, int maxnb, int rings,
+                                                    const unsigned char* __restrict__ nbc,
+                                                    const unsigned short* __restrict__ ncol, int S, int maxnb, int rings,
                                                     int* __restrict__ plist, int4* __restrict__ pcnt,
                                                     unsigned short* __restrict__ tlist,
                                                     unsigned char* __restrict__ tcnt, int* err) {
@@ -1410,11 +1433,18 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     // (kListU rows each), most first, so that the lanes of a wave mostly run
     // the same number of passes over their lists.  Within a group the order is
     // the segment order (a stable counting sort), so every per-tile sum over
-    // the staged particles rounds the same way in every run.  An LDS table maps
-    // slot -> staged index (open addressing, kPairHash buckets for at most
-    // kPairCap keys, so a probe always reaches an empty bucket).
-    __shared__ int hkey[kPairHash];  // slot + 1; 0: empty
-    __shared__ unsigned short hval[kPairHash];
+    // the staged particles rounds the same way in every run.
+    // List entries name a neighbour by its cell relative to the particle's and
+    // its index in that cell; a map of the tile's cells (owned and rings, local
+    // coordinates relative to column c0 - rings and row r0 - rings, modulo nc)
+    // gives each cell's first staged index (segment order).  A cell's particles
+    // are consecutive there (one segment holds the cell, in slot order), so the
+    // first of each run of equal cells writes the map.
+    constexpr int kMapSide = 32 + 6;  // pT <= 32, rings <= 3
+    __shared__ unsigned short mst[kMapSide * kMapSide];
+    __shared__ unsigned short ckey[kPairCap];  // local cell, segment order
+    __shared__ unsigned short lcell[kPairCap];  // local cell, final order
+    __shared__ unsigned short qn_of[kPairCap];  // final index of each segment index
     __shared__ int lq[kPairCap];   // slot of each staged index
     __shared__ int lq0[kPairCap];  // slots in segment order
     __shared__ unsigned char gq[kPairCap];
@@ -1423,12 +1453,27 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     constexpr int kGroups = 128;  // list-row groups 0 .. maxnb / kListU (maxnb <= 248)
     __shared__ int gcnt[3][kGroups];
     const int ng = maxnb / kListU + 1;
-    for (int h = threadIdx.x; h < kPairHash; h += BS) hkey[h] = 0;
+    const int sx = (c1 - c0) + 2 * rings, sy = nr + 2 * rings, cl0 = c0 - rings, rl0 = r0 - rings;
+    auto wrap = [&](int x) { return x < 0 ? x + nc : (x >= nc ? x - nc : x); };
     for (int e = threadIdx.x; e < 3 * kGroups; e += BS) gcnt[e / kGroups][e % kGroups] = 0;
     for (int g = threadIdx.x; g < ns; g += BS) {
         const int q0 = so[g], a0 = sa[g];
         const int m = min(sn[g], kPairCap - q0);
-        for (int i = 0; i < m; ++i) lq0[q0 + i] = a0 + i;
+        // the segment's row, local (the same for all its particles)
+        int row;
+        if (g < nr) {
+            row = r0 + g;
+        } else {
+            int k = 1;
+            while (g >= first(k + 1)) ++k;
+            const int e = g - first(k);
+            row = e < 4 ? ((e >> 1) ? r1 + k - 1 : r0 - k) : r0 - k + 1 + ((e - 4) >> 1);
+        }
+        const int ly = wrap(wrap(row) - rl0);
+        for (int i = 0; i < m; ++i) {
+            lq0[q0 + i] = a0 + i;
+            ckey[q0 + i] = (unsigned short)ly;
+        }
     }
     __syncthreads();
     const int listed = n[rings - 1];
@@ -1437,27 +1482,41 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         while (q >= n[r]) ++r;
         return r;
     };
-    // group counts per ring, and per 64-particle chunk one ballot of each bit
-    // of the group number (every wave's lanes cover one chunk at a time)
+    // local cells of all staged particles; list lengths, group counts per ring,
+    // and per 64-particle chunk one ballot of each bit of the group number
+    // (every wave's lanes cover one chunk at a time)
     static_assert(kGroups == 128, "group numbers have 7 bits");
     const int nbits = ng > 1 ? 32 - __clz(ng - 1) : 0;
     __shared__ unsigned long long gbit[kPairCap / 64][7];
-    for (int base = threadIdx.x & ~63; base < listed; base += BS) {
+    constexpr unsigned short kOutside = 0xffff;
+    for (int base = threadIdx.x & ~63; base < tot; base += BS) {
         const int q = base + (threadIdx.x & 63);
         int g = 0;
-        if (q < listed) {
-            const int nn = nbc[lq0[q]];
-            g = (nn + kListU - 1) / kListU;
-            cntq[q] = (unsigned char)nn;
-            gq[q] = (unsigned char)g;
-            atomicAdd(&gcnt[ring_of(q)][g], 1);
+        if (q < tot) {
+            const int slot = lq0[q];
+            const int lx = wrap(ncol[slot] - cl0), ly = ckey[q];
+            ckey[q] = lx < sx && ly < sy ? (unsigned short)(ly * kMapSide + lx) : kOutside;
+            if (q < listed) {
+                const int nn = nbc[slot];
+                g = (nn + kListU - 1) / kListU;
+                cntq[q] = (unsigned char)nn;
+                gq[q] = (unsigned char)g;
+                atomicAdd(&gcnt[ring_of(q)][g], 1);
+            }
         }
-        for (int b = 0; b < nbits; ++b) {
-            const unsigned long long m = __ballot((g >> b) & 1);
-            if ((threadIdx.x & 63) == 0) gbit[base >> 6][b] = m;
+        if (base < listed) {
+            for (int b = 0; b < nbits; ++b) {
+                const unsigned long long m = __ballot((g >> b) & 1);
+                if ((threadIdx.x & 63) == 0) gbit[base >> 6][b] = m;
+            }
         }
     }
     __syncthreads();
+    for (int q = threadIdx.x; q < tot; q += BS) {
+        const unsigned short k = ckey[q];
+        if (k == kOutside) atomicOr(err, ERR_NLIST);
+        else if (q == 0 || ckey[q - 1] != k) mst[k] = (unsigned short)q;
+    }
     if (threadIdx.x < rings) {  // first staged index of each (ring, group), most groups first
         const int r = threadIdx.x;
         int acc = r == 0 ? 0 : n[r - 1];
@@ -1468,12 +1527,11 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
         }
     }
     __syncthreads();
-    auto bucket = [](int k) { return ((unsigned int)k * 2654435761u) >> (32 - kPairHashBits); };
-    int* list = plist + (long long)t * kPairCap;
     // A listed particle's place: its group's first index plus the number of
     // earlier particles of the same ring and group in segment order, counted
     // chunk by chunk from the group-bit ballots over the ring's range, so that
     // the staged order does not depend on the timing of atomics.
+    int* list = plist + (long long)t * kPairCap;
     auto below = [](int e) { return e >= 64 ? ~0ull : (1ull << e) - 1ull; };
     for (int q = threadIdx.x; q < tot; q += BS) {
         int qn = q;
@@ -1489,53 +1547,53 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
                 rank += __popcll(m);
             }
             qn = rank;
+            qn_of[q] = (unsigned short)qn;
+            lcnt[qn] = cntq[q];
+            lcell[qn] = ckey[q];
         }
         const int slot = lq0[q];
         lq[qn] = slot;
         list[qn] = slot;
-        if (q < listed) lcnt[qn] = cntq[q];
-        unsigned int h = bucket(slot);
-        while (atomicCAS(&hkey[h], 0, slot + 1) != 0) h = (h + 1) & (kPairHash - 1);
-        hval[h] = (unsigned short)qn;
     }
     __syncthreads();
     // particles of every ring but the last: neighbour counts and lists as staged
     // indices.  The first kListPre list rows of a particle are read together
     // (they always exist, see list_rows), further ones kListU at a time.
-    const int slot0 = R.slot0, nrep = R.n;
     unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
-    auto map_entry = [&](int s, int q, int j, int off, int lim) {
-        int kr = (s - slot0) + off;
-        kr = kr < 0 ? kr + nrep : (kr >= nrep ? kr - nrep : kr);
-        const int k = slot0 + kr;
-        unsigned int h = bucket(k);
-        int key;
-        while ((key = hkey[h]) != k + 1 && key != 0) h = (h + 1) & (kPairHash - 1);
-        int loc = key == 0 ? -1 : (int)hval[h];
-        if (loc < 0 || loc >= lim) {
-            atomicOr(err, ERR_NLIST);
-            loc = 0;
-        }
-        tl[(long long)j * kPairCap + q] = (unsigned short)loc;
-    };
     for (int q = threadIdx.x; q < listed; q += blockDim.x) {
         const int s = lq[q];
         const int nn = lcnt[q];
+        const int own_cell = lcell[q];
         int first_rows[kListPre];
         list_rows(nbl, (unsigned int)s, (unsigned int)S, first_rows);
         tcnt[(long long)t * kPairCap + q] = (unsigned char)nn;
-        int ring = 0;
-        while (q >= n[ring]) ++ring;
+        const int ring = ring_of(q);
         const int lim = ring + 1 < rings ? n[ring + 1] : tot;
+        const int lx = own_cell % kMapSide, ly = own_cell / kMapSide;
+        auto map_entry = [&](int e, int j) {
+            const unsigned int u = (unsigned int)(unsigned short)e;
+            const int code = (int)(u >> 12), idx = (int)(u & 4095u);
+            const int xx = lx + code % 3 - 1, yy = ly + code / 3 - 1;
+            int loc = -1;
+            if (own_cell != kOutside && code < 9 && xx >= 0 && xx < sx && yy >= 0 && yy < sy) {
+                const int k = (int)mst[yy * kMapSide + xx] + idx;
+                loc = k < listed ? (int)qn_of[k] : k;
+            }
+            if (loc < 0 || loc >= lim) {
+                atomicOr(err, ERR_NLIST);
+                loc = 0;
+            }
+            tl[(long long)j * kPairCap + q] = (unsigned short)loc;
+        };
 #pragma unroll
         for (int j = 0; j < kListPre; ++j)
-            if (j < nn) map_entry(s, q, j, first_rows[j], lim);
+            if (j < nn) map_entry(first_rows[j], j);
         for (int j0 = kListPre; j0 < nn; j0 += kListU) {
             int rows[kListU];
             list_rows(nbl, (unsigned int)s + (unsigned int)j0 * (unsigned int)S, (unsigned int)S, rows);
 #pragma unroll
             for (int u = 0; u < kListU; ++u)
-                if (j0 + u < nn) map_entry(s, q, j0 + u, rows[u], lim);
+                if (j0 + u < nn) map_entry(rows[u], j0 + u);
         }
     }
 }
@@ -1926,6 +1984,7 @@ struct lj_md {
     int* d_tinfo = nullptr;
     short* nbl = nullptr;     // neighbour lists (step kernel 3)
     unsigned char* nbc = nullptr;
+    unsigned short* ncol = nullptr;  // cell column of each slot (tile list builder)
     // two ordinary steps per launch (step kernel 3)
     bool two_step = false;
     bool three_step = false;          // also three ordinary steps per launch (implies two_step)
@@ -2241,15 +2300,21 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
     b.snap_n = md->snap[o ^ 1];
     hipLaunchKernelGGL(k_place, dim3((S + 255) / 256), dim3(256), 0, st, (const int*)md->cs, (const int*)md->key,
                        (const int*)md->perm, (const int*)md->permid, S, b, md->variant == 3 ? nullptr : md->cellof);
-    if (md->variant == 3)
-        hipLaunchKernelGGL(k_nlist_build, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
+    // the tile lists take entries by cell and index within the cell; the
+    // one-step kernel takes slot offsets
+    if (md->variant == 3 && md->two_step)
+        hipLaunchKernelGGL(k_nlist_build<true>, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
                            (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
-                           md->maxnb, md->nbl, md->nbc, md->pref, md->d_err);
+                           md->maxnb, md->nbl, md->nbc, md->ncol, md->pref, md->d_err);
+    else if (md->variant == 3)
+        hipLaunchKernelGGL(k_nlist_build<false>, dim3((S + 255) / 256), dim3(256), 0, st, (const double2*)b.pos_n,
+                           (const int*)md->cs, (const RepDev*)md->d_reps, (const int*)md->d_tile_rep, md->BS, S,
+                           md->maxnb, md->nbl, md->nbc, (unsigned short*)nullptr, md->pref, md->d_err);
     if (md->two_step)
         hipLaunchKernelGGL(k_pair_build<kPairBuildBS>, dim3(md->npt), dim3(kPairBuildBS), 0, st, (const int*)md->cs,
                            (const RepDev*)md->d_reps, (const int*)md->d_ptrep, (const short*)md->nbl,
-                           (const unsigned char*)md->nbc, S, md->maxnb, md->rings, md->plist, md->pcnt, md->tlist,
-                           md->tcnt, md->d_err);
+                           (const unsigned char*)md->nbc, (const unsigned short*)md->ncol, S, md->maxnb, md->rings,
+                           md->plist, md->pcnt, md->tlist, md->tcnt, md->d_err);
     md->ppar ^= 1;
     md->opar ^= 1;
     md->vpar ^= 1;
@@ -2597,7 +2662,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
                 const double ppc = std::max((double)d.n / ((double)d.nc * d.nc), 1e-9);
                 int T = (int)std::floor(std::sqrt((double)target / ppc)) - 2 * rings;
                 T = std::min(std::min(T, 32), d.nc - 2 * rings);
-                if (T < tmin) return false;
+                if (T < tmin || d.nc > 65535) return false;  // cell columns are 16-bit in the tile lists
                 d.pT = T;
                 d.pts = (d.nc + T - 1) / T;
                 d.pnt = d.pts * d.pts;
@@ -2656,7 +2721,7 @@ extern "C" mdlg_status lj_md_init_batch(lj_md** out, int32_t n_rep, const lj_par
         if (ok && md->two_step)
             ok = A(dalloc(&md->d_ptrep, md->npt)) && A(dalloc(&md->plist, (size_t)md->npt * kPairCap)) &&
                  A(dalloc(&md->pcnt, md->npt)) && A(dalloc(&md->tlist, (size_t)md->npt * md->maxnb * kPairCap)) &&
-                 A(dalloc(&md->tcnt, (size_t)md->npt * kPairCap));
+                 A(dalloc(&md->tcnt, (size_t)md->npt * kPairCap)) && A(dalloc(&md->ncol, md->S));
     }
     if (!ok) return destroy_on_fail(md, fail(MDLG_ENOMEM, "lj_md_init: device allocation failed"));
 
@@ -3162,7 +3227,7 @@ extern "C" void lj_md_destroy(lj_md* md) {
     if (!md) return;
     clear_graphs(md);
     if (md->cap) (void)hipStreamDestroy(md->cap);
-    void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->pref, md->d_hpart, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
+    void* ptrs[] = {md->d_reps, md->d_tile_rep, md->d_ttile_rep, md->d_tinfo, md->nbl, md->nbc, md->ncol, md->pref, md->d_hpart, md->pos[0], md->pos[1], md->vel[0], md->vel[1], md->img[0],
                     md->img[1], md->id[0], md->id[1], md->snap[0], md->snap[1], md->key, md->rank, md->perm, md->permid,
                     md->cellof, md->cnt, md->cs, md->bsum, md->d_err, md->d_epart, md->d_eout, md->d_vmax,
                     md->d_mpart, md->d_event_k, md->d_ptrep, md->plist, md->pcnt, md->tlist, md->tcnt};
