@@ -1321,16 +1321,16 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
     }
 }
 
-// Per tile, after the neighbour lists: the staged slots, as contiguous slot
-// ranges of the row-major cell order (owned rows; then ring 1: the rows above
-// and below and the cells left and right of each owned row; then ring 2 and,
-// with three rings, ring 3 likewise one cell further out each), the counts
-// (owned, up to ring 1, up to ring 2, all), and for the particles of every ring
-// but the last their neighbour counts and lists as staged indices,
-// [tile][row j][staged index q].  Neighbour lists reach one cell, so the
-// neighbours of a ring-k particle lie within ring k + 1.  A tile that stages
-// more than kPairCap particles raises ERR_TILE, a neighbour outside that
-// bound ERR_NLIST.
+// Per tile, after the neighbour lists (entries by cell and index within the
+// cell): the staged slots, as contiguous slot ranges of the row-major cell
+// order (owned rows; then ring 1: the rows above and below and the cells left
+// and right of each owned row; then ring 2 and, with three rings, ring 3
+// likewise one cell further out each), the counts (owned, up to ring 1, up to
+// ring 2, all), and for the particles of every ring but the last their
+// neighbour counts and lists as staged indices, [tile][row j][staged index q].
+// Neighbour lists reach one cell, so the neighbours of a ring-k particle lie
+// within ring k + 1.  A tile that stages more than kPairCap particles raises
+// ERR_TILE, a neighbour outside that bound ERR_NLIST.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, const RepDev* __restrict__ reps,
                                                     const int* __restrict__ ptrep, const short* __restrict__ nbl,
