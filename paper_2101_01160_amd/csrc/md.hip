@@ -740,19 +740,26 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
                                                      unsigned char* __restrict__ nbc, unsigned short* __restrict__ ncol,
                                                      double2* __restrict__ pref, int* err) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const RepDev& R = reps[tile_rep[min(s, S - 1) / BSt]];
+    const bool act = s < S && s - R.slot0 < R.n;
+    const double2 p = pos[act ? s : 0];
+    const int nc = R.nc;
+    const int cx = cell_coord(p.x, R.inv_w, nc);
+    const int cy = cell_coord(p.y, R.inv_w, nc);
+    // a wave whose particles all lie in cells 1 .. nc - 2 has no candidate
+    // across the periodic edge (candidates within one cell: separations below
+    // 2 w <= L / 2 for nc >= 4): the minimum image would leave them unchanged,
+    // bit for bit
+    const bool inner = nc >= 4 && cx >= 1 && cx < nc - 1 && cy >= 1 && cy < nc - 1;
+    const bool interior = __ballot(act && !inner) == 0ull;
     if (s >= S) return;
-    const RepDev& R = reps[tile_rep[s / BSt]];
-    if (s - R.slot0 >= R.n) {
+    if (!act) {
         nbc[s] = 0;
         return;
     }
-    const double2 p = pos[s];
     pref[s] = p;
-    const int nc = R.nc;
     const double invL = 1.0 / R.L;
     const double rl2 = R.w * R.w;
-    const int cx = cell_coord(p.x, R.inv_w, nc);
-    const int cy = cell_coord(p.y, R.inv_w, nc);
     if (CELL) ncol[s] = (unsigned short)cx;
     int cnt = 0;
     for (int oy = -1; oy <= 1; ++oy) {
@@ -774,8 +781,11 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
             const int k = t < na ? a0 + t : b0 + (t - na);
             if (k == s) continue;
             const double2 q = pos[k];
-            const double dx = min_image_rint(p.x - q.x, R.L, invL);
-            const double dy = min_image_rint(p.y - q.y, R.L, invL);
+            double dx = p.x - q.x, dy = p.y - q.y;
+            if (!interior) {
+                dx = min_image_rint(dx, R.L, invL);
+                dy = min_image_rint(dy, R.L, invL);
+            }
             if (within_list_range(dx, dy, rl2)) {
                 int e;
                 if (CELL) {
