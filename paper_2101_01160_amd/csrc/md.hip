@@ -1752,12 +1752,19 @@ __global__ void k_put_img(const int2* __restrict__ img_in, const int* __restrict
     if (s < S && id[s] >= 0) img[s] = img_in[id[s]];
 }
 
-// Exclusive scan of n ints (cnt) into out[0..n] (out[n] = total), three passes
-// over tiles of 4096 elements (1024 threads x 4).
-constexpr int kScanTile = 4096;
+// Exclusive scan of n ints (cnt) into out[0..n] (out[n] = total), in tiles of
+// kScanTile elements (kScanBS threads x 4): per-tile totals, then each tile's
+// offset and its elements (above kScanDirect tiles, a pass over the totals
+// in between).
+constexpr int kScanBS = 256;
+constexpr int kScanTile = 4 * kScanBS;
 constexpr int kScanDirect = 2048;  // up to this many tiles, two kernels (each tile sums the totals before it)
 
-__device__ __forceinline__ int block_excl_scan_1024(int v, int* lds, int& total) {
+// Exclusive scan over the block of NT threads; lds holds 2 NT / 64 ints.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int* lds, int& total) {
+    static_assert(NT % 64 == 0 && NT <= 1024, "whole waves, at most 16");
+    constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int x = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -1767,29 +1774,43 @@ __device__ __forceinline__ int block_excl_scan_1024(int v, int* lds, int& total)
     if (lane == 63) lds[wid] = x;
     __syncthreads();
     if (wid == 0) {
-        int w = lane < 16 ? lds[lane] : 0;
-        for (int o = 1; o < 16; o <<= 1) {
+        int w = lane < NW ? lds[lane] : 0;
+        for (int o = 1; o < NW; o <<= 1) {
             int y = __shfl_up(w, o, 64);
             if (lane >= o) w += y;
         }
-        if (lane < 16) lds[16 + lane] = w;
+        if (lane < NW) lds[NW + lane] = w;
     }
     __syncthreads();
-    total = lds[31];
-    const int wave_off = wid > 0 ? lds[16 + wid - 1] : 0;
+    total = lds[2 * NW - 1];
+    const int wave_off = wid > 0 ? lds[NW + wid - 1] : 0;
     const int res = wave_off + x - v;
     __syncthreads();
     return res;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_reduce(const int* __restrict__ in, long long n, int* __restrict__ bsum) {
-    __shared__ int lds[32];
+// A thread's four elements from base: one 16-byte load when all lie below n
+// (base is a multiple of 4 and the arrays are 16-byte aligned), else one by one.
+__device__ __forceinline__ void load4(const int* __restrict__ in, long long base, long long n, int (&v)[4]) {
+    if (base + 3 < n) {
+        const int4 q = *reinterpret_cast<const int4*>(in + base);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+        for (int j = 0; j < 4; ++j) v[j] = base + j < n ? in[base + j] : 0;
+    }
+}
+
+__global__ __launch_bounds__(kScanBS) void k_scan_reduce(const int* __restrict__ in, long long n,
+                                                         int* __restrict__ bsum) {
+    __shared__ int lds[2 * kScanBS / 64];
     const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
-    int s = 0;
-    for (int j = 0; j < 4; ++j)
-        if (base + j < n) s += in[base + j];
+    int v[4];
+    load4(in, base, n, v);
     int total;
-    block_excl_scan_1024(s, lds, total);
+    block_excl_scan<kScanBS>(v[0] + v[1] + v[2] + v[3], lds, total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
@@ -1800,7 +1821,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(int* bsum, int nb) {
         const int i = b0 + threadIdx.x;
         const int v = i < nb ? bsum[i] : 0;
         int total;
-        const int ex = block_excl_scan_1024(v, lds, total);
+        const int ex = block_excl_scan<1024>(v, lds, total);
         if (i < nb) bsum[i] = carry + ex;
         carry += total;
     }
@@ -1808,31 +1829,38 @@ __global__ __launch_bounds__(1024) void k_scan_top(int* bsum, int nb) {
 
 // With `sums`, boff holds the tile totals and each block adds up those of the
 // tiles before it (short scans, see kScanDirect); else boff holds the tile
-// offsets from k_scan_top.
-__global__ __launch_bounds__(1024) void k_scan_final(int* __restrict__ in, long long n,
-                                                     const int* __restrict__ boff, int* __restrict__ out, int sums) {
-    __shared__ int lds[32];
+// offsets from k_scan_top.  The counts are cleared for the next rebuild.
+__global__ __launch_bounds__(kScanBS) void k_scan_final(int* __restrict__ in, long long n,
+                                                        const int* __restrict__ boff, int* __restrict__ out,
+                                                        int sums) {
+    __shared__ int lds[2 * kScanBS / 64];
+    const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
+    int v[4];
+    load4(in, base, n, v);
     int tile_off;
     if (sums) {
         int part = 0;
-        for (int b = threadIdx.x; b < (int)blockIdx.x; b += 1024) part += boff[b];
-        block_excl_scan_1024(part, lds, tile_off);
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBS) part += boff[b];
+        block_excl_scan<kScanBS>(part, lds, tile_off);
     } else {
         tile_off = boff[blockIdx.x];
     }
-    const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
-    int v[4];
-    int s = 0;
-    for (int j = 0; j < 4; ++j) {
-        v[j] = base + j < n ? in[base + j] : 0;
-        if (base + j < n) in[base + j] = 0;  // counts start from zero at the next rebuild
-        s += v[j];
-    }
     int total;
-    int ex = block_excl_scan_1024(s, lds, total) + tile_off;
+    int ex = block_excl_scan<kScanBS>(v[0] + v[1] + v[2] + v[3], lds, total) + tile_off;
+    int o[4];
     for (int j = 0; j < 4; ++j) {
-        if (base + j < n) out[base + j] = ex;
+        o[j] = ex;
         ex += v[j];
+    }
+    if (base + 3 < n) {
+        *reinterpret_cast<int4*>(in + base) = make_int4(0, 0, 0, 0);
+        *reinterpret_cast<int4*>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+    } else {
+        for (int j = 0; j < 4; ++j)
+            if (base + j < n) {
+                in[base + j] = 0;
+                out[base + j] = o[j];
+            }
     }
     if (base <= n - 1 && n - 1 < base + 4) out[n] = ex;  // thread holding the last element
 }
@@ -2287,10 +2315,10 @@ hipError_t launch_rebuild(lj_md* md, hipStream_t st) {
         }
     }
     const int nb = (C + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, (const int*)md->cnt, (long long)C, md->bsum);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBS), 0, st, (const int*)md->cnt, (long long)C, md->bsum);
     const int direct = nb <= kScanDirect ? 1 : 0;
     if (!direct) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, md->bsum, nb);
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, st, md->cnt, (long long)C, (const int*)md->bsum,
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBS), 0, st, md->cnt, (long long)C, (const int*)md->bsum,
                        md->cs, direct);
     if (md->variant == 2)
         hipLaunchKernelGGL(k_tile_info, dim3((md->TT + 255) / 256), dim3(256), 0, st, (const int*)md->cs,
