@@ -1938,8 +1938,13 @@ __global__ void k_init_slots(const double* __restrict__ pos0, const double* __re
     snap[s] = pos[s];
 }
 
-__global__ void k_vmax(const double2* __restrict__ vel, const int* __restrict__ id, int S,
-                       unsigned long long* out) {
+// Largest squared speed, as the bits of a non-negative double (ordered as
+// integers): a wave maximum, the block's in LDS, and one atomic per block
+// only where it raises the value already there (one address takes every
+// block's update, so most blocks skip it).
+__global__ __launch_bounds__(256) void k_vmax(const double2* __restrict__ vel, const int* __restrict__ id, int S,
+                                              unsigned long long* out) {
+    __shared__ double wmax[4];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     double v2 = 0.0;
     if (s < S && id[s] >= 0) {
@@ -1948,7 +1953,13 @@ __global__ void k_vmax(const double2* __restrict__ vel, const int* __restrict__ 
         if (!isfinite(v2)) v2 = 1e300;
     }
     for (int o = 32; o > 0; o >>= 1) v2 = fmax(v2, __shfl_xor(v2, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v2));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double b = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(b);
+        if (bits > __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(out, bits);
+    }
 }
 
 __global__ void k_copy_d2(const double2* __restrict__ src, double2* __restrict__ dst, int S) {
