@@ -833,7 +833,8 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
 // by 0 (a valid index) before they are used as one.
 constexpr int kListU = 2;              // fused kernels (lists ordered by length within a tile)
 constexpr int kListUOne = 4;           // one-step kernel (slot order: fewer, longer passes keep more loads in flight)
-constexpr int kListPre = 2 * kListU;  // rows loaded ahead for a thread's first particle (maxnb >= 16)
+constexpr int kListPre = 3 * kListU;  // rows loaded ahead for a thread's first particle (maxnb >= 16)
+static_assert(kListPre % kListU == 0, "whole passes of the fused kernels' rows loaded ahead");
 
 template <int N, typename Entry>
 __device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsigned int off, unsigned int stride,
@@ -842,18 +843,18 @@ __device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsign
     for (int u = 0; u < N; ++u) kk[u] = list[off + u * stride];
 }
 
-// With use_first, the first kListPre rows come from `first`.
+// With use_first, the rows of the passes that lie within the first kListPre
+// come from `first`.
 template <bool F32, int U, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
                                             double& fy, const int (&first)[kListPre], bool use_first) {
-    static_assert(kListPre % U == 0, "whole passes of rows loaded ahead");
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
     for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
         int kk[U];
-        if (use_first && j0 < kListPre) {
+        if (use_first && j0 + U <= kListPre) {
 #pragma unroll
             for (int b = 0; b < kListPre / U; ++b)
                 if (j0 == b * U) {
