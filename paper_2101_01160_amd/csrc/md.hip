@@ -833,7 +833,8 @@ __global__ __launch_bounds__(256) void k_nlist_build(const double2* __restrict__
 // by 0 (a valid index) before they are used as one.
 constexpr int kListU = 2;              // fused kernels (lists ordered by length within a tile)
 constexpr int kListUOne = 4;           // one-step kernel (slot order: fewer, longer passes keep more loads in flight)
-constexpr int kListPre = 3 * kListU;  // rows loaded ahead for a thread's first particle (maxnb >= 16)
+constexpr int kListPre = 4 * kListU;  // rows loaded ahead for a thread's first particle (maxnb >= 16)
+constexpr int kListPreEvent = 2 * kListU;  // the same in the event and binning launches
 static_assert(kListPre % kListU == 0, "whole passes of the fused kernels' rows loaded ahead");
 
 template <int N, typename Entry>
@@ -843,20 +844,20 @@ __device__ __forceinline__ void list_rows(const Entry* __restrict__ list, unsign
     for (int u = 0; u < N; ++u) kk[u] = list[off + u * stride];
 }
 
-// With use_first, the rows of the passes that lie within the first kListPre
-// come from `first`.
-template <bool F32, int U, typename Entry, typename Fetch>
+// With use_first, the rows of the passes that lie within the first P come
+// from `first`.
+template <bool F32, int U, int P, typename Entry, typename Fetch>
 __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __restrict__ list, unsigned int off,
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
-                                            double& fy, const int (&first)[kListPre], bool use_first) {
+                                            double& fy, const int (&first)[P], bool use_first) {
     double ax = 0.0, ay = 0.0;
     float bx = 0.0f, by = 0.0f;
     for (int j0 = 0; j0 < nn; j0 += U, off += U * stride) {
         int kk[U];
-        if (use_first && j0 + U <= kListPre) {
+        if (use_first && j0 + U <= P) {
 #pragma unroll
-            for (int b = 0; b < kListPre / U; ++b)
+            for (int b = 0; b < P / U; ++b)
                 if (j0 == b * U) {
 #pragma unroll
                     for (int u = 0; u < U; ++u) kk[u] = first[b * U + u];
@@ -910,9 +911,9 @@ __device__ __forceinline__ void nlist_force(double2 p, int nn, const Entry* __re
                                             unsigned int stride, Fetch fetch, bool interior, double L, double invL,
                                             double rc2, double eps24, float rc2f, float eps24f, double& fx,
                                             double& fy) {
-    const int none[kListPre] = {};
-    nlist_force<F32, U>(p, nn, list, off, stride, fetch, interior, L, invL, rc2, eps24, rc2f, eps24f, fx, fy, none,
-                     false);
+    const int none[1] = {};
+    nlist_force<F32, U, 1>(p, nn, list, off, stride, fetch, interior, L, invL, rc2, eps24, rc2f, eps24f, fx, fy,
+                           none, false);
 }
 
 // Velocity-Verlet update with the force at the current position: complete
@@ -1055,6 +1056,7 @@ constexpr int kPairTarget = 520;   // staged particles aimed at when choosing th
 constexpr int kPairTarget3 = 580;  // the same with three rings
 constexpr int kPairSeg = 248;      // row segments of one tile: 7 pT + 24 <= 248 for pT <= 32, three rings
 constexpr int kPairBuildBS = 256;  // threads of the tile list builder
+constexpr int kPairPre = 4;        // list rows it reads ahead per particle (maxnb >= 16)
 
 // End of a coarse step: per replica and component, the fixed-order sum over
 // the replica's tiles of the histogram and moment partials is added to the
@@ -1167,7 +1169,9 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
     const int s_first = list[qf];
     const int s_second = qf + BS < kPairCap ? list[qf + BS] : 0;
     const int nn_first = tc[qf];
-    int pre[kListPre];
+    // the event and binning launches, short of registers, load fewer rows ahead
+    constexpr int PRE = (CG || BIN) ? kListPreEvent : kListPre;
+    int pre[PRE];
     list_rows(tl, (unsigned int)qf, SL, pre);
     const int4 c = a.pcnt[t];
     const int own = c.x;
@@ -1216,7 +1220,7 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
             const int nn = firstq ? nn_first : tc[q];
             auto fetch = [&](int k) { return src[k]; };
             double fx, fy;
-            nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24,
+            nlist_force<F32, kListU, PRE>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24,
                                      R.rc2f, R.eps24f, fx, fy, pre, firstq);
             int wx, wy;
             const double2 pn = interior ? vv_update<false, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
@@ -1255,7 +1259,7 @@ __global__ __launch_bounds__(BS, 8) void k_step_fused(StepArgs a) {
         const int nn = firstq ? nn_first : tc[q];
         auto fetch = [&](int k) { return last[k]; };
         double fx, fy;
-        nlist_force<F32, kListU>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
+        nlist_force<F32, kListU, PRE>(p, nn, tl, (unsigned int)q, SL, fetch, interior, L, invL, R.rc2, R.eps24, R.rc2f,
                                  R.eps24f, fx, fy, pre, firstq);
         int wx, wy;
         const double2 pn = interior ? vv_update<FIRST, false>(p, v, fx, fy, a.dt, a.hdt, L, wx, wy)
@@ -1568,14 +1572,14 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
     }
     __syncthreads();
     // particles of every ring but the last: neighbour counts and lists as staged
-    // indices.  The first kListPre list rows of a particle are read together
+    // indices.  The first kPairPre list rows of a particle are read together
     // (they always exist, see list_rows), further ones kListU at a time.
     unsigned short* tl = tlist + (long long)t * maxnb * kPairCap;
     for (int q = threadIdx.x; q < listed; q += blockDim.x) {
         const int s = lq[q];
         const int nn = lcnt[q];
         const int own_cell = lcell[q];
-        int first_rows[kListPre];
+        int first_rows[kPairPre];
         list_rows(nbl, (unsigned int)s, (unsigned int)S, first_rows);
         tcnt[(long long)t * kPairCap + q] = (unsigned char)nn;
         const int ring = ring_of(q);
@@ -1597,9 +1601,9 @@ __global__ __launch_bounds__(BS) void k_pair_build(const int* __restrict__ cs, c
             tl[(long long)j * kPairCap + q] = (unsigned short)loc;
         };
 #pragma unroll
-        for (int j = 0; j < kListPre; ++j)
+        for (int j = 0; j < kPairPre; ++j)
             if (j < nn) map_entry(first_rows[j], j);
-        for (int j0 = kListPre; j0 < nn; j0 += kListU) {
+        for (int j0 = kPairPre; j0 < nn; j0 += kListU) {
             int rows[kListU];
             list_rows(nbl, (unsigned int)s + (unsigned int)j0 * (unsigned int)S, (unsigned int)S, rows);
 #pragma unroll
