@@ -98,6 +98,31 @@ def test_100_steps_match_oracle(n, phi, kT, kw):
     sysm.close()
 
 
+@pytest.mark.parametrize("n,nc", [(51, 3), (86, 4), (140, 5)])
+def test_smallest_boxes_match_oracle(n, nc):
+    """Boxes of three to five cells per side (phi = 0.4, cells of rc + skin):
+    every cell's neighbourhood wraps across the periodic edges, and below
+    four cells per side two cells apart are less than L / 2 apart, so the
+    minimum image is taken for every pair.  100 steps against the oracle,
+    with a coarse-graining event every 10 steps (counts exact)."""
+    print(f"small box n={n}", flush=True)
+    pos0, vel0, L = mi.initial_state(n, 0.4, 5.0, 11)
+    sysm = gpu_system(pos0, vel0, L)
+    assert sysm.info()["cells_per_side"] == nc
+    acc = sysm.attach_cg(7, 10)
+    sysm.step(100)
+    pos, vel, img = (_np(t) for t in sysm.state())
+    sysm.check()
+    oacc = omd.CGAccum(7)
+    po, vo, io, _ = omd.md_run(pos0, vel0, np.zeros((n, 2), np.int64), L, 100, cg=oacc, s_cg=10)
+    assert np.array_equal(img, io)
+    up, uo = pos + L * img, po + L * io
+    assert np.max(np.abs(up - uo)) <= 1e-10 * np.abs(uo).max()
+    assert np.max(np.abs(vel - vo)) <= 1e-10 * np.abs(vo).max()
+    assert np.array_equal(_np(acc.counts)[0], oacc.counts)
+    sysm.close()
+
+
 def test_energy_and_momentum_match_oracle_and_are_conserved():
     n = 2000
     pos0, vel0, L = mi.initial_state(n, 0.4, 20.0, 5)
